@@ -1,0 +1,213 @@
+// Exact geometric predicates for float32 points (device code, gfx950).
+//
+// The paper's kernels compute point-to-line distances and side tests in
+// plain float (section 4, Table 1 "float dist[n]"). Here every side test and
+// every farthest-point comparison is exact, so the hull does not depend on
+// rounding: a float32 evaluation with a proven error bound decides almost
+// all cases and an exact float64 expansion decides the rest.
+//
+// Build with -ffp-contract=off: the bounds below assume that every
+// operation is rounded separately and that nothing is reassociated.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sqh {
+
+// Orientation of p against the directed edge o -> e:
+//   orient = (ex - ox) * (py - oy) - (ey - oy) * (px - ox)
+// > 0: p left of o->e;  < 0: p right of o->e (outside a counter-clockwise
+// hull edge);  0: collinear.
+struct Edge {
+    float ox, oy, ex, ey;  // end points
+    float dx, dy;          // fl(ex - ox), fl(ey - oy)
+    int fwd;               // 1 if e is lexicographically after o
+};
+
+__device__ __forceinline__ Edge make_edge(float ox, float oy, float ex, float ey)
+{
+    Edge E;
+    E.ox = ox; E.oy = oy; E.ex = ex; E.ey = ey;
+    E.dx = ex - ox; E.dy = ey - oy;
+    E.fwd = (ex > ox) || (ex == ox && ey > oy);
+    return E;
+}
+
+// ---- float32 filter -------------------------------------------------------
+//
+// With u = 2^-24, a1 = py-oy, b1 = px-ox (each rounded once, |delta| <= u;
+// a difference that lands in the subnormal range is exact), P = fl(dx*a1),
+// Q = fl(dy*b1) (relative error u plus an absolute underflow term
+// eta <= 2^-150 each) and d = fl(P - Q):
+//   |(P - Q) - orient| <= ((1+u)^3 - 1)/(1-u)^3 * (|P| + |Q|) + 2.0001 eta
+//                       <= 3.0001 u S + 2.0001 eta,       S = |P| + |Q|.
+// fl(P - Q) has the sign of P - Q, and |P - Q| >= |d| / (1 + u). Hence with
+//   es = fl(fl(2^-22 * fl(S)) + TAU),   TAU = 2^-140 (>> 4 eta),
+// |d| > es proves sign(d) == sign(orient):  es/(1+u) >= 3.9999 u S + 0.9999
+// TAU exceeds the error bound (the rounding of fl(S) and of the sum are
+// inside the margin). The same es also bounds the error of d itself:
+//   |d - orient| <= 4.0002 u S + 2.0001 eta <= 2 es,
+// so [d - 2es, d + 2es] encloses the exact orientation; the farthest-point
+// comparison uses that interval. Any overflow makes S or d non-finite and
+// the comparisons below false, which routes the case to the exact path.
+constexpr float kFilterScale = 0x1p-22f;
+constexpr float kFilterTau = 0x1p-140f;
+
+struct Orient32 {
+    float d;   // fl(orient)
+    float es;  // sign certificate bound; 2*es bounds |d - orient|
+};
+
+__device__ __forceinline__ Orient32 orient32(const Edge& E, float px, float py)
+{
+    float a1 = py - E.oy;
+    float b1 = px - E.ox;
+    float P = E.dx * a1;
+    float Q = E.dy * b1;
+    Orient32 r;
+    r.d = P - Q;
+    float S = fabsf(P) + fabsf(Q);
+    r.es = S * kFilterScale + kFilterTau;
+    return r;
+}
+
+// ---- exact float64 path ---------------------------------------------------
+//
+// The product of two float32 values is exact in float64 (24+24 significand
+// bits; exponents stay inside the normal float64 range), so orient is an
+// exact sum of six float64 terms. Its sign is the sign of the most
+// significant nonzero component of the nonoverlapping expansion built with
+// Knuth's TwoSum and Shewchuk's Grow-Expansion (J. R. Shewchuk, "Adaptive
+// Precision Floating-Point Arithmetic and Fast Robust Geometric Predicates",
+// 1997). Every partial sum is a multiple of 2^-298, so TwoSum never
+// underflows.
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    e = (a - av) + (b - bv);
+    s = x;
+}
+
+template <int K>
+__device__ __forceinline__ int expansion_sign(const double (&t)[K])
+{
+    double e[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double q = t[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            double s, h;
+            two_sum(q, e[j], s, h);
+            e[j] = h;
+            q = s;
+        }
+        e[i] = q;
+    }
+    int sg = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) sg = e[j] > 0.0 ? 1 : (e[j] < 0.0 ? -1 : sg);
+    return sg;
+}
+
+// sign of orient(o, e, p), exactly:
+//   ex*py - ex*oy - ox*py - ey*px + ey*ox + oy*px
+__device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey, float px, float py)
+{
+    double t[6];
+    t[0] = (double)ex * (double)py;
+    t[1] = -((double)ex * (double)oy);
+    t[2] = -((double)ox * (double)py);
+    t[3] = -((double)ey * (double)px);
+    t[4] = (double)ey * (double)ox;
+    t[5] = (double)oy * (double)px;
+    return expansion_sign(t);
+}
+
+// sign of area(P) - area(Q) for the edge o -> e, where area(X) = -orient(o,e,X):
+//   (ex-ox)(qy-py) - (ey-oy)(qx-px)
+//   = ex*qy - ex*py - ox*qy + ox*py - ey*qx + ey*px + oy*qx - oy*px
+__device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float ey,
+                                           float px, float py, float qx, float qy)
+{
+    double t[8];
+    t[0] = (double)ex * (double)qy;
+    t[1] = -((double)ex * (double)py);
+    t[2] = -((double)ox * (double)qy);
+    t[3] = (double)ox * (double)py;
+    t[4] = -((double)ey * (double)qx);
+    t[5] = (double)ey * (double)px;
+    t[6] = (double)oy * (double)qx;
+    t[7] = -((double)oy * (double)px);
+    return expansion_sign(t);
+}
+
+// Exact sign of orient(o, e, p), filtered. `fp64_only` skips the filter.
+// Also returns the float32 estimate for the farthest-point interval.
+__device__ __forceinline__ int orient_sign(const Edge& E, float px, float py, bool fp64_only,
+                                           Orient32& o, uint32_t& n_exact)
+{
+    o = orient32(E, px, py);
+    if (!fp64_only && fabsf(o.d) > o.es) return o.d > 0.0f ? 1 : -1;
+    ++n_exact;
+    return orient_exact(E.ox, E.oy, E.ex, E.ey, px, py);
+}
+
+// ---- farthest-point candidates ---------------------------------------------
+//
+// A candidate is a point strictly right of its segment's edge. `a` is the
+// float32 estimate of its area -orient (positive), `w` a bound on the
+// estimate's error, `pos` its slot in the pass input (-1: no candidate).
+struct Cand {
+    float a, w;
+    float x, y;
+    int id;
+    int pos;
+};
+
+__device__ __forceinline__ Cand no_cand()
+{
+    Cand c;
+    c.a = 0.0f; c.w = 0.0f; c.x = 0.0f; c.y = 0.0f; c.id = 0x7fffffff; c.pos = -1;
+    return c;
+}
+
+// Total order "P is farther from the edge than Q" (section 4.4.1 finds the
+// farthest point; the paper does not say how ties are broken). Exact area
+// first; among points at equal area (they lie on one line parallel to the
+// edge) the one earliest along o -> e wins -- an end point of that run and
+// hence a hull vertex; coincident points: the lowest index. A total order
+// makes the reduction result independent of the reduction tree.
+__device__ __forceinline__ bool beats(const Edge& E, const Cand& P, const Cand& Q, bool fp64_only,
+                                      uint32_t& n_exact)
+{
+    if (Q.pos < 0) return P.pos >= 0;
+    if (P.pos < 0) return false;
+    if (!fp64_only) {
+        // fl(x) > fl(y) implies x > y (rounding is monotone), so these
+        // certify area(P) >= P.a - P.w > Q.a + Q.w >= area(Q).
+        if (P.a - P.w > Q.a + Q.w) return true;
+        if (Q.a - Q.w > P.a + P.w) return false;
+    }
+    ++n_exact;
+    int s = area_cmp_exact(E.ox, E.oy, E.ex, E.ey, P.x, P.y, Q.x, Q.y);
+    if (s != 0) return s > 0;
+    if (P.x == Q.x && P.y == Q.y) return P.id < Q.id;
+    bool p_first = (P.x < Q.x) || (P.x == Q.x && P.y < Q.y);
+    return E.fwd ? p_first : !p_first;
+}
+
+// Candidate for a point known to be strictly right of E (orient < 0).
+__device__ __forceinline__ Cand make_cand(const Orient32& o, float x, float y, int id, int pos)
+{
+    Cand c;
+    c.a = -o.d;
+    c.w = 2.0f * o.es;
+    c.x = x; c.y = y; c.id = id; c.pos = pos;
+    return c;
+}
+
+}  // namespace sqh

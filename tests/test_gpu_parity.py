@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Hull index lists are integer results: the bar is bit-exact equality with the
+oracle (Andrew's monotone chain on exact integers / exact expansions).
+"""
+import glob
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hull_exact as he
+from paper_1501_04706_amd import sqh, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a HIP device"
+    h = sqh.Hull(0)
+    yield h
+    h.close()
+
+
+def gpu_hull(H, xy):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)).to("cuda")
+    return [int(v) for v in H.hull(t).cpu().numpy()]
+
+
+def load_golden(path):
+    pts, hull = [], None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("hull:"):
+            hull = [int(t) for t in line.split(":")[1].split()]
+        else:
+            pts.append([float(v) for v in line.split()])
+    return np.array(pts, np.float32).reshape(-1, 2), hull
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.txt"))))
+def test_golden(H, path):
+    say(f"golden {os.path.basename(path)}")
+    xy, expect = load_golden(path)
+    assert gpu_hull(H, xy) == expect
+
+
+def test_degenerate(H):
+    say("degenerate")
+    cases = [
+        np.zeros((0, 2), np.float32),
+        np.array([[3, 4]], np.float32),
+        np.array([[1, 1], [0, 0]], np.float32),
+        np.array([[1, 1], [1, 1]], np.float32),
+        np.array([[0, 0], [1, 0], [0, 1]], np.float32),
+        np.full((5000, 2), 0.5, np.float32),
+        np.stack([np.arange(3000), np.arange(3000) * 3], 1).astype(np.float32)[::-1].copy(),
+        np.array([[-0.0, 0.0], [0.0, -0.0], [1, 0], [0, 1]], np.float32),
+    ]
+    for xy in cases:
+        assert gpu_hull(H, xy) == he.hull(xy), xy[:4]
+
+
+def test_small_random_grids(H):
+    # many tiny sets on small integer grids: duplicates, collinear runs, ties
+    rng = np.random.default_rng(123)
+    for it in range(300):
+        n = int(rng.integers(1, 60))
+        k = int(rng.integers(1, 7))
+        xy = (rng.integers(-k, k + 1, size=(n, 2)) * 0.5).astype(np.float32)
+        if it == 0:
+            say("small random grids")
+        assert gpu_hull(H, xy) == he.hull(xy), (it, xy.tolist())
+
+
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 4095, 4097, 6144, 123457])
+def test_tile_boundaries(H, n):
+    say(f"tile boundaries n={n}")
+    for kind in ("square", "disk", "circle", "grid"):
+        xy = workloads.make(kind, n, n)
+        assert gpu_hull(H, xy) == [int(v) for v in oracle.c_hull(xy)], kind
+
+
+def test_parabola_all_vertices(H):
+    say("parabola")
+    rng = np.random.default_rng(9)
+    x = rng.permutation(np.arange(-2048, 2049))
+    xy = np.stack([x, x * x], 1).astype(np.float32)
+    assert gpu_hull(H, xy) == [int(i) for i in np.argsort(x)]
+
+
+def test_config0_square_100k(H):
+    say("square n=100000 seed 0")
+    xy = workloads.square(100_000, 0)
+    h = gpu_hull(H, xy)
+    assert h == he.hull(xy)
+    assert len(h) == 31
+
+
+@pytest.mark.parametrize("kind", ["square", "disk", "circle", "grid"])
+@pytest.mark.parametrize("n", [1_000_000])
+def test_workloads_1m(H, kind, n):
+    say(f"{kind} n={n}")
+    xy = workloads.make(kind, n, 0)
+    assert gpu_hull(H, xy) == [int(v) for v in oracle.c_hull(xy)]
+
+
+def test_fp64_only_identical(H):
+    say("fp64-only mode")
+    xy = workloads.circle(300_000, 3)
+    a = gpu_hull(H, xy)
+    H.set_precision(sqh.SQH_FP64_ONLY)
+    try:
+        b = gpu_hull(H, xy)
+    finally:
+        H.set_precision(sqh.SQH_FP32_FILTER)
+    assert a == b == [int(v) for v in oracle.c_hull(xy)]
+
+
+def test_deterministic(H):
+    say("determinism")
+    xy = workloads.grid(500_000, 4)
+    a = gpu_hull(H, xy)
+    b = gpu_hull(H, xy)
+    assert a == b
+
+
+def test_batched_matches_single(H):
+    import torch
+    say("batched")
+    rng = np.random.default_rng(77)
+    sizes = [0, 1, 2, 3, 64, 0, 2048, 2049, 5000, 1, 100_000, 7, 4096, 333]
+    sizes += [int(v) for v in rng.integers(0, 3000, size=40)]
+    kinds = ["square", "disk", "circle", "grid"]
+    parts = [workloads.make(kinds[i % 4], s, 100 + i) for i, s in enumerate(sizes)]
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    xy = np.concatenate(parts, 0).astype(np.float32)
+    out, out_off = H.hull_batched(torch.from_numpy(xy).cuda(), torch.from_numpy(off).cuda())
+    out = out.cpu().numpy()
+    out_off = out_off.cpu().numpy()
+    for s, p in enumerate(parts):
+        got = [int(v) for v in out[out_off[s]:out_off[s + 1]]]
+        assert got == he.hull(p) if len(p) < 3000 else got == [int(v) for v in oracle.c_hull(p)], s
+
+
+def test_errors(H):
+    import torch
+    say("error paths")
+    xy = workloads.square(10_000, 1)
+    xy[77, 1] = np.nan
+    with pytest.raises(sqh.SqhError) as ei:
+        H.hull(torch.from_numpy(xy).cuda())
+    assert ei.value.code == sqh.SQH_EINVAL
+    xy = workloads.disk(50_000, 2)
+    t = torch.from_numpy(xy).cuda()
+    expect = [int(v) for v in oracle.c_hull(xy)]
+    out = torch.empty(5, dtype=torch.int32, device="cuda")
+    ws = H.workspace(len(xy), 1)
+    rc, h = sqh.sqh_hull(H.ctx, t, len(xy), out, 5, ws, ws.numel())
+    assert rc == sqh.SQH_ECAPACITY and h == len(expect)
+    assert [int(v) for v in out.cpu().numpy()] == expect[:5]
+    rc, h = sqh.sqh_hull(H.ctx, t, len(xy), out, 5, ws, 1000)
+    assert rc == sqh.SQH_ENOMEM

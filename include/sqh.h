@@ -60,17 +60,26 @@ extern "C" {
 
 typedef struct sqh_ctx sqh_ctx;
 
-/* Per-call counters of the last sqh_hull / sqh_hull_batched call. */
+#define SQH_MAX_TIMED_PASSES 64
+
+/* Per-call counters of the last sqh_hull / sqh_hull_batched call. Kernel
+ * times come from HIP events recorded on the call's stream around each
+ * launch. */
 typedef struct sqh_stats {
-    int64_t passes;           /* segmented passes after the first split */
+    int64_t passes;           /* segmented passes after the first compaction */
     int64_t points;           /* input points */
+    int64_t first_survivors;  /* points kept by the first compaction */
     int64_t survivors_total;  /* sum over passes of points entering the pass */
     int64_t orient_evals;     /* orientation predicates evaluated */
     int64_t orient_exact;     /* ... of which took the exact float64 path */
     int64_t cmp_exact;        /* farthest-point comparisons decided exactly */
     int64_t hull_size;        /* total hull vertices (all sets) */
     int64_t max_segments;     /* largest number of active segments in a pass */
-    double  ms_total;         /* device time of the last call (HIP events) */
+    double  ms_total;         /* device time of the whole call */
+    double  ms_seed, ms_split, ms_first, ms_pass, ms_table, ms_emit;  /* kernel times */
+    int64_t pass_points[SQH_MAX_TIMED_PASSES];    /* points entering pass k */
+    int64_t pass_segments[SQH_MAX_TIMED_PASSES];  /* segments in pass k */
+    double  pass_ms[SQH_MAX_TIMED_PASSES];        /* kernel time of pass k */
 } sqh_stats;
 
 /*
@@ -137,6 +146,13 @@ int sqh_hull_batched(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, 
 
 /* Counters of the last hull call on this context. */
 int sqh_get_stats(const sqh_ctx *ctx, sqh_stats *out);
+
+/* Diagnostics: with the environment variable SQH_TRACE=1 set before
+ * sqh_create, every call records per-workgroup timestamps (100 MHz device
+ * clock) at phase boundaries; this copies up to max_entries of them
+ * (8 per workgroup, workgroup-major) into host array `out` and returns the
+ * number copied (0 when tracing is off), or SQH_EINVAL. */
+int sqh_get_trace(const sqh_ctx *ctx, uint64_t *out, int max_entries);
 
 /* Static description of a return code. */
 const char *sqh_strerror(int code);

@@ -1,6 +1,8 @@
 // Host driver and C ABI of libsqh (see include/sqh.h for the contract).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -14,16 +16,16 @@ using namespace sqh;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kTile = kRows * 64 * kWaves;  // positions per tile of the segmented kernels
-constexpr int kLBWords = 4;                 // max look-back words per tile and kind (k_first)
+constexpr int kMaxGrid = kMaxChunks;  // workgroups of the persistent kernel (upper bound)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    int64_t N, nsets, scap, rcap, W, ntcap;
+    int64_t N, nsets, scap, rcap, W;
     size_t x[2], y[2], id[2];
     size_t gstart, sets, recs, rec_cid, segs[2], seg_cid[2], vstart[2];
-    size_t bitmap, vidx, wprefix, lb, err, stats, sv, total;
+    size_t bitmap, vidx, vlist, wprefix, slots, ctab, bar, err, stats, sv, info;
+    int64_t vcap;
     size_t bytes;
 };
 
@@ -39,8 +41,6 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     L.scap = std::max<int64_t>(s_first, (2 * N + 2) / 3) + 8;
     L.rcap = std::max<int64_t>(4 * nsets, 2 * L.scap) + 8;
     L.W = (N + 63) / 64 + 1;
-    const int64_t items = std::max<int64_t>(std::max<int64_t>(N, L.rcap), L.W);
-    L.ntcap = (items + std::min(kTile, kScanTile) - 1) / std::min(kTile, kScanTile) + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     for (int b = 0; b < 2; ++b) {
@@ -59,12 +59,16 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     }
     L.bitmap = take(sizeof(uint64_t) * (size_t)L.W);
     L.vidx = take(sizeof(int) * (size_t)std::max<int64_t>(N, 1));
+    L.vcap = std::min<int64_t>(N + 8, kSmallHull);
+    L.vlist = take(sizeof(int2) * (size_t)L.vcap);
     L.wprefix = take(sizeof(int) * (size_t)L.W);
-    L.lb = take(sizeof(uint64_t) * 2 * kLBWords * (size_t)L.ntcap);
+    L.slots = take(sizeof(ChunkSlot<4>) * (size_t)kMaxGrid);
+    L.ctab = take(sizeof(Pair) * (size_t)kMaxGrid);
+    L.bar = take(sizeof(GridBar));
     L.err = take(sizeof(int));
     L.stats = take(sizeof(uint32_t) * 4 * kStatSlots);
     L.sv = take(sizeof(int) * 4);
-    L.total = take(sizeof(int));
+    L.info = take(sizeof(HullInfo));
     L.bytes = o;
     return true;
 }
@@ -75,37 +79,16 @@ struct sqh_ctx {
     int device = 0;
     int cus = 0;
     int fp64 = 0;
-    int grid_seed = 0, grid_split = 0, grid_first = 0, grid_pass = 0, grid_table = 0, grid_emit = 0;
+    int grid = 0;  // co-resident workgroups of k_hull
+    int trace = 0; // SQH_TRACE=1: per-workgroup timestamps in the info block
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    int* pinned = nullptr;  // host readback buffer
+    HullInfo* hinfo = nullptr;  // pinned host copy of the info block
+    uint32_t* hstats = nullptr;  // pinned host copy of the counters
+    int* herr = nullptr;
     sqh_stats stats{};
 };
 
 namespace {
-
-template <class K>
-int coop_grid(K kernel, int cus)
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), kBlock, 0) !=
-        hipSuccess)
-        return 0;
-    return std::max(1, nb) * cus;
-}
-
-template <class K, class... Args>
-hipError_t coop_launch(K kernel, int grid, hipStream_t s, Args... args)
-{
-    void* argv[] = {static_cast<void*>(&args)...};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(std::max(1, grid)),
-                                      dim3(kBlock), argv, 0, s);
-}
-
-int grid_for(int cap, int64_t items, int tile)
-{
-    const int64_t nt = (items + tile - 1) / tile;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, nt));
-}
 
 #define HIP_OK(expr)                                       \
     do {                                                   \
@@ -124,123 +107,100 @@ int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t
     HIP_OK(hipSetDevice(ctx->device));
 
     char* ws = static_cast<char*>(d_ws);
-    float* X[2] = {reinterpret_cast<float*>(ws + L.x[0]), reinterpret_cast<float*>(ws + L.x[1])};
-    float* Y[2] = {reinterpret_cast<float*>(ws + L.y[0]), reinterpret_cast<float*>(ws + L.y[1])};
-    int* I[2] = {reinterpret_cast<int*>(ws + L.id[0]), reinterpret_cast<int*>(ws + L.id[1])};
-    int* gstart = reinterpret_cast<int*>(ws + L.gstart);
-    SetInfo* sets = reinterpret_cast<SetInfo*>(ws + L.sets);
-    Seg* recs = reinterpret_cast<Seg*>(ws + L.recs);
-    int* rec_cid = reinterpret_cast<int*>(ws + L.rec_cid);
-    Seg* segs[2] = {reinterpret_cast<Seg*>(ws + L.segs[0]), reinterpret_cast<Seg*>(ws + L.segs[1])};
-    int* seg_cid[2] = {reinterpret_cast<int*>(ws + L.seg_cid[0]), reinterpret_cast<int*>(ws + L.seg_cid[1])};
-    int* vstart[2] = {reinterpret_cast<int*>(ws + L.vstart[0]), reinterpret_cast<int*>(ws + L.vstart[1])};
-    uint64_t* bitmap = reinterpret_cast<uint64_t*>(ws + L.bitmap);
-    int* vidx = reinterpret_cast<int*>(ws + L.vidx);
-    int* wprefix = reinterpret_cast<int*>(ws + L.wprefix);
-    uint64_t* lb = reinterpret_cast<uint64_t*>(ws + L.lb);
-    int* err = reinterpret_cast<int*>(ws + L.err);
-    uint32_t* stats = reinterpret_cast<uint32_t*>(ws + L.stats);
-    int* sv = reinterpret_cast<int*>(ws + L.sv);  // {S0, V0, S1, V1}
-    int* total = reinterpret_cast<int*>(ws + L.total);
-    const size_t lb_bytes = sizeof(uint64_t) * 2 * kLBWords * (size_t)L.ntcap;
-    const int n = (int)N, G = (int)nsets, ntcap = (int)L.ntcap, fp64 = ctx->fp64;
-    int* pin = ctx->pinned;
+    auto at = [&](size_t off) { return static_cast<void*>(ws + off); };
+    HullArgs a;
+    a.xy = reinterpret_cast<const float2*>(d_xy);
+    a.N = (int)N;
+    a.G = (int)nsets;
+    a.set_off = d_set_off;
+    a.out = d_out;
+    a.cap = out_cap;
+    a.out_off = d_out_off;
+    for (int b = 0; b < 2; ++b) {
+        a.X[b] = static_cast<float*>(at(L.x[b]));
+        a.Y[b] = static_cast<float*>(at(L.y[b]));
+        a.I[b] = static_cast<int*>(at(L.id[b]));
+        a.segs[b] = static_cast<Seg*>(at(L.segs[b]));
+        a.seg_cid[b] = static_cast<int*>(at(L.seg_cid[b]));
+        a.vstart[b] = static_cast<int*>(at(L.vstart[b]));
+    }
+    a.gstart = static_cast<int*>(at(L.gstart));
+    a.sets = static_cast<SetInfo*>(at(L.sets));
+    a.recs = static_cast<Seg*>(at(L.recs));
+    a.rec_cid = static_cast<int*>(at(L.rec_cid));
+    a.sv = static_cast<int*>(at(L.sv));
+    a.bitmap = static_cast<uint64_t*>(at(L.bitmap));
+    a.vidx = static_cast<int*>(at(L.vidx));
+    a.vlist = static_cast<int2*>(at(L.vlist));
+    a.vcap = (int)L.vcap;
+    a.wprefix = static_cast<int*>(at(L.wprefix));
+    a.W = (int)((N + 63) / 64);
+    a.slots = at(L.slots);
+    a.ctab = static_cast<Pair*>(at(L.ctab));
+    a.bar = static_cast<GridBar*>(at(L.bar));
+    a.err = static_cast<int*>(at(L.err));
+    a.stats = static_cast<uint32_t*>(at(L.stats));
+    a.info = static_cast<HullInfo*>(at(L.info));
+    a.fp64 = ctx->fp64;
+    a.timing = ctx->trace ? 2 : 1;
 
-    ctx->stats = sqh_stats{};
-    ctx->stats.points = N;
     HIP_OK(hipEventRecord(ctx->ev0, st));
-    HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
-    HIP_OK(hipMemsetAsync(stats, 0, sizeof(uint32_t) * 4 * kStatSlots, st));
-    HIP_OK(hipMemsetAsync(bitmap, 0, sizeof(uint64_t) * (size_t)L.W, st));
-    HIP_OK(hipMemsetAsync(recs, 0, sizeof(Seg) * (size_t)(4 * nsets), st));
-    if (d_set_off) {
-        k_prep_sets<<<(G + 1 + 255) / 256, 256, 0, st>>>(d_set_off, G, N, gstart, err);
-    } else {
-        k_single_set<<<1, 64, 0, st>>>(gstart, n);
-    }
-    HIP_OK(hipGetLastError());
-
-    // seed: lexmin / lexmax per set
-    HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
     {
-        PolSeed pol{reinterpret_cast<const float2*>(d_xy), gstart, sets, err};
-        HIP_OK(coop_launch(k_tiles<PolSeed>, grid_for(ctx->grid_seed, N, kTile), st, pol, (const int*)nullptr, n,
-                           (const int*)nullptr, G, ntcap, lb, err, stats));
-    }
-    HIP_OK(hipMemcpyAsync(pin, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (pin[0] & (kErrNonFinite | kErrBounds)) return SQH_EINVAL;
-    if (pin[0]) return SQH_EDEVICE;
-
-    // first split: side counts and farthest point per side
-    HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-    {
-        PolSplit pol{reinterpret_cast<const float2*>(d_xy), gstart, sets, bitmap, vidx, fp64};
-        HIP_OK(coop_launch(k_tiles<PolSplit>, grid_for(ctx->grid_split, N, kTile), st, pol, (const int*)nullptr, n,
-                           (const int*)nullptr, G, ntcap, lb, err, stats));
-    }
-    // first compaction into four child segments per set
-    HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-    {
-        PolFirst pol{reinterpret_cast<const float2*>(d_xy), gstart, sets, X[0], Y[0], I[0], recs, rec_cid, bitmap,
-                     vidx, fp64};
-        HIP_OK(coop_launch(k_tiles<PolFirst>, grid_for(ctx->grid_first, N, kTile), st, pol, (const int*)nullptr, n,
-                           (const int*)nullptr, G, ntcap, lb, err, stats));
-    }
-    HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-    HIP_OK(coop_launch(k_table, grid_for(ctx->grid_table, 4 * nsets, kScanTile), st, (const Seg*)recs,
-                       (const int*)rec_cid, (const int*)nullptr, 0, (int)(4 * nsets), segs[0], seg_cid[0], vstart[0],
-                       sv, ntcap, lb, err));
-
-    int cur = 0;
-    for (int pass = 0;; ++pass) {
-        HIP_OK(hipMemcpyAsync(pin, sv + 2 * cur, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        const int S = pin[0], V = pin[1];
-        if (S <= 0) break;
-        ctx->stats.passes += 1;
-        ctx->stats.survivors_total += V;
-        ctx->stats.max_segments = std::max<int64_t>(ctx->stats.max_segments, S);
-        const int nxt = cur ^ 1;
-        HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-        {
-            PolPass pol{segs[cur], seg_cid[cur], vstart[cur], X[cur], Y[cur], I[cur], X[nxt], Y[nxt], I[nxt],
-                        recs, rec_cid, bitmap, vidx, fp64};
-            HIP_OK(coop_launch(k_tiles<PolPass>, grid_for(ctx->grid_pass, V, kTile), st, pol,
-                               (const int*)(sv + 2 * cur + 1), 0, (const int*)(sv + 2 * cur), 0, ntcap, lb, err,
-                               stats));
-        }
-        HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-        HIP_OK(coop_launch(k_table, grid_for(ctx->grid_table, 2 * (int64_t)S, kScanTile), st, (const Seg*)recs,
-                           (const int*)rec_cid, (const int*)(sv + 2 * cur), 2, 0, segs[nxt], seg_cid[nxt],
-                           vstart[nxt], sv + 2 * nxt, ntcap, lb, err));
-        cur = nxt;
-    }
-
-    HIP_OK(hipMemsetAsync(lb, 0, lb_bytes, st));
-    const int W = (int)((N + 63) / 64);
-    HIP_OK(coop_launch(k_emit, grid_for(ctx->grid_emit, W, kScanTile), st, (const uint64_t*)bitmap, (const int*)vidx,
-                       W, d_out, out_cap, wprefix, total, ntcap, lb, err));
-    if (d_out_off) {
-        k_out_offsets<<<(G + 1 + 255) / 256, 256, 0, st>>>(gstart, G, n, bitmap, wprefix, total, d_out_off);
+        const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
+        const int grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
+        k_reset<<<grid, 256, 0, st>>>(a);
         HIP_OK(hipGetLastError());
     }
+    void* argv[] = {static_cast<void*>(&a)};
+    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull), dim3(ctx->grid), dim3(kBlock), argv,
+                                      0, st));
     HIP_OK(hipEventRecord(ctx->ev1, st));
-    HIP_OK(hipMemcpyAsync(pin, total, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(pin + 1, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(pin + 2, stats, sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ctx->hinfo, a.info, ctx->trace ? sizeof(HullInfo) : offsetof(HullInfo, trace),
+                          hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ctx->hstats, a.stats, sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ctx->herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    const int64_t h = pin[0];
-    const int e = pin[1];
-    const uint32_t* sp = reinterpret_cast<const uint32_t*>(pin + 2);
-    for (int i = 0; i < kStatSlots; ++i) {
-        ctx->stats.orient_evals += sp[4 * i + 0];
-        ctx->stats.orient_exact += sp[4 * i + 1];
-        ctx->stats.cmp_exact += sp[4 * i + 2];
+
+    const HullInfo& hi = *ctx->hinfo;
+    const int e = *ctx->herr;
+    sqh_stats& S = ctx->stats;
+    S = sqh_stats{};
+    S.points = N;
+    S.passes = hi.passes;
+    S.first_survivors = hi.first_v;
+    for (int p = 0; p < hi.passes && p < kMaxInfoPasses; ++p) {
+        S.survivors_total += hi.pass_v[p];
+        S.max_segments = std::max<int64_t>(S.max_segments, hi.pass_s[p]);
+        if (p < SQH_MAX_TIMED_PASSES) {
+            S.pass_points[p] = hi.pass_v[p];
+            S.pass_segments[p] = hi.pass_s[p];
+        }
     }
-    ctx->stats.hull_size = h;
+    for (int i = 0; i < kStatSlots; ++i) {
+        S.orient_evals += ctx->hstats[4 * i + 0];
+        S.orient_exact += ctx->hstats[4 * i + 1];
+        S.cmp_exact += ctx->hstats[4 * i + 2];
+    }
+    // device timestamps (100 MHz constant clock) at phase ends, block 0
+    if (hi.nstamps > 1) {
+        const double tick_ms = 1e-5;
+        auto dt = [&](int i) { return (double)(hi.stamp[i] - hi.stamp[i - 1]) * tick_ms; };
+        for (int i = 1; i < hi.nstamps && i < kMaxStamps; ++i) {
+            const int tag = hi.stamp_tag[i];
+            if (tag == 1) S.ms_seed += dt(i);
+            else if (tag == 2) S.ms_split += dt(i);
+            else if (tag == 3) S.ms_first += dt(i);
+            else if (tag == 4) S.ms_emit += dt(i);
+            else if (tag >= 100) {
+                S.ms_pass += dt(i);
+                if (tag - 100 < SQH_MAX_TIMED_PASSES) S.pass_ms[tag - 100] = dt(i);
+            }
+        }
+    }
+    const int64_t h = hi.h_total;
+    S.hull_size = h;
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) ctx->stats.ms_total = ms;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
     if (h_total) *h_total = h;
     if (e & (kErrNonFinite | kErrBounds)) return SQH_EINVAL;
     if (e) return SQH_EDEVICE;
@@ -264,15 +224,23 @@ int sqh_create(sqh_ctx** out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return SQH_EDEVICE; }
     c->cus = prop.multiProcessorCount;
-    c->grid_seed = coop_grid(k_tiles<PolSeed>, c->cus);
-    c->grid_split = coop_grid(k_tiles<PolSplit>, c->cus);
-    c->grid_first = coop_grid(k_tiles<PolFirst>, c->cus);
-    c->grid_pass = coop_grid(k_tiles<PolPass>, c->cus);
-    c->grid_table = coop_grid(k_table, c->cus);
-    c->grid_emit = coop_grid(k_emit, c->cus);
-    if (!c->grid_seed || !c->grid_split || !c->grid_first || !c->grid_pass || !c->grid_table || !c->grid_emit ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 4096, hipHostMallocDefault) != hipSuccess) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_hull), kBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1) {
+        delete c;
+        return SQH_EDEVICE;
+    }
+    c->grid = std::min(kMaxGrid, per_cu * c->cus);
+    {
+        const char* t = getenv("SQH_TRACE");
+        c->trace = t && t[0] == '1';
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->hstats), sizeof(uint32_t) * 4 * kStatSlots,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->herr), sizeof(int), hipHostMallocDefault) != hipSuccess) {
         sqh_destroy(c);
         return SQH_EDEVICE;
     }
@@ -285,7 +253,9 @@ void sqh_destroy(sqh_ctx* c)
     if (!c) return;
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->hinfo) (void)hipHostFree(c->hinfo);
+    if (c->hstats) (void)hipHostFree(c->hstats);
+    if (c->herr) (void)hipHostFree(c->herr);
     delete c;
 }
 
@@ -320,6 +290,15 @@ int sqh_hull_batched(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     if (h_total) *h_total = 0;
     return run(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, h_total, d_ws, ws_bytes,
                static_cast<hipStream_t>(stream));
+}
+
+int sqh_get_trace(const sqh_ctx* c, uint64_t* out, int max_entries)
+{
+    if (!c || !out || max_entries < 0) return SQH_EINVAL;
+    if (!c->trace) return 0;
+    const int n = std::min(max_entries, c->grid * 8);
+    for (int i = 0; i < n; ++i) out[i] = c->hinfo->trace[i / 8][i % 8];
+    return n;
 }
 
 int sqh_get_stats(const sqh_ctx* c, sqh_stats* out)

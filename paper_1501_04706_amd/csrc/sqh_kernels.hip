@@ -17,7 +17,7 @@
 #include <stdint.h>
 
 #include "sqh_pred.hpp"
-#include "sqh_tile.hpp"
+#include "sqh_chunk.hpp"
 #include "sqh_types.hpp"
 
 namespace sqh {
@@ -29,7 +29,7 @@ __device__ __forceinline__ int search_le(const int* start, int q, int lo, int hi
     // largest g in [lo, hi] with start[g] <= q (start[lo] <= q is assumed)
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= q) lo = mid;
+        if (gld(start + mid) <= q) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -39,10 +39,14 @@ __device__ __forceinline__ int search_le(const int* start, int q, int lo, int hi
 // point and no other vertex of its set uses, increasing along the ring
 // (counter-clockwise from the set's lexmin point). The emit step orders
 // vertices by key.
-__device__ __forceinline__ void record_vertex(uint64_t* bitmap, int* vidx, int key, int id)
+struct HullInfo;
+__device__ void note_vertex(HullInfo* info, int2* vlist, int key, int id);
+__device__ __forceinline__ void record_vertex(uint64_t* bitmap, int* vidx, int2* vlist, HullInfo* info, int key,
+                                              int id)
 {
     atomicOr((unsigned long long*)&bitmap[key >> 6], 1ull << (key & 63));
-    vidx[key] = id;
+    gst(vidx + key, id);
+    note_vertex(info, vlist, key, id);
 }
 
 // ============================================================ k_seed ==
@@ -57,49 +61,50 @@ struct PolSeed {
     const int* gstart;
     SetInfo* sets;
     int* err;
+    int G;
 
-    __device__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
-    __device__ int group_start(int g) const { return gstart[g]; }
-    __device__ int group_end(int g) const { return gstart[g + 1]; }
-    __device__ Ctx ctx(int g) const { return Ctx{gstart[g]}; }
-    __device__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
+    __device__ __forceinline__ Ctx ctx(int g) const { return Ctx{gld(gstart + g)}; }
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
-        const float2 v = xy[q];
+        const float2 v = gld(xy + q);
         x = v.x; y = v.y; id = q - c.base;
     }
-    __device__ int classify(const Ctx&, int, int q, float x, float y, int id, Cand& k, Counters&) const
+    __device__ __forceinline__ int classify(const Ctx&, int, int q, float x, float y, int id, Cand& k, Counters&) const
     {
         if (!(isfinite(x) && isfinite(y))) {
             atomicOr(err, kErrNonFinite);
             return 0;
         }
-        k.a = 0.0f; k.w = 0.0f; k.x = x; k.y = y; k.id = id; k.pos = q;
+        k.a = 0.0f; k.w = 0.0f; k.x = x; k.y = y; k.id = id;
         return 3;  // candidate for both lexmin (bucket 0) and lexmax (bucket 1)
     }
     // bucket 0: lexicographically smaller wins; bucket 1: larger wins; ties
     // (coincident points): lower index. Values compare as floats (-0 == +0).
-    __device__ bool beats(const Ctx&, int k, const Cand& P, const Cand& Q, Counters&) const
+    __device__ __forceinline__ int beats_fast(const Ctx&, int k, const Cand& P, const Cand& Q) const
     {
-        if (Q.pos < 0) return P.pos >= 0;
-        if (P.pos < 0) return false;
-        if (P.x == Q.x && P.y == Q.y) return P.id < Q.id;
-        const bool less = (P.x < Q.x) || (P.x == Q.x && P.y < Q.y);
-        return k == 0 ? less : !less;
+        const bool less = (P.x < Q.x) | ((P.x == Q.x) & (P.y < Q.y));
+        const bool more = (P.x > Q.x) | ((P.x == Q.x) & (P.y > Q.y));
+        const bool eq = (P.x == Q.x) & (P.y == Q.y);
+        const bool w = (k == 0 ? less : more) | (eq & (P.id < Q.id));
+        const bool r = (Q.id < 0) ? (P.id >= 0) : ((P.id >= 0) & w);
+        return r ? 1 : 0;
     }
-    __device__ Cand fetch_cand(const Ctx& c, int, int pos, Counters&) const
+    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters&) const
     {
-        const float2 v = xy[pos];
-        Cand k;
-        k.a = 0.0f; k.w = 0.0f; k.x = v.x; k.y = v.y; k.id = pos - c.base; k.pos = pos;
-        return k;
+        return beats_fast(c, k, P, Q) > 0;
     }
-    __device__ int place(const Ctx&, int, int, int) const { return 0; }
-    __device__ void store(int, float, float, int) const {}
-    __device__ void finalize(const Ctx&, int g, const Agg<NB>& a) const
+    __device__ __forceinline__ int place(const Ctx&, int, int, int) const { return 0; }
+    __device__ __forceinline__ void store(int, float, float, int) const {}
+    __device__ __forceinline__ void finalize(const Ctx&, int g, const Agg<NB>& a) const
     {
-        SetInfo& s = sets[g];
-        s.ax = a.best[0].x; s.ay = a.best[0].y; s.aid = a.best[0].id; s.apos = a.best[0].pos;
-        s.bx = a.best[1].x; s.by = a.best[1].y; s.bid = a.best[1].id; s.bpos = a.best[1].pos;
+        SetInfo s = gld(sets + g);
+        s.ax = a.best[0].x; s.ay = a.best[0].y; s.aid = a.best[0].id;
+        s.bx = a.best[1].x; s.by = a.best[1].y; s.bid = a.best[1].id;
+        gst(sets + g, s);
     }
 };
 
@@ -117,68 +122,67 @@ struct PolSplit {
     SetInfo* sets;
     uint64_t* bitmap;
     int* vidx;
+    int2* vlist;
+    HullInfo* info;
     int fp64;
+    int G;
 
-    __device__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
-    __device__ int group_start(int g) const { return gstart[g]; }
-    __device__ int group_end(int g) const { return gstart[g + 1]; }
-    __device__ Ctx ctx(int g) const
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
+    __device__ __forceinline__ Ctx ctx(int g) const
     {
-        const SetInfo& s = sets[g];
+        const SetInfo s = gld(sets + g);
         Ctx c;
         c.ab = make_edge(s.ax, s.ay, s.bx, s.by);
         c.ba = make_edge(s.bx, s.by, s.ax, s.ay);
-        c.base = gstart[g];
+        c.base = gld(gstart + g);
         // lexmin and lexmax coincide only if every point sits at one position
         c.skip = (s.ax == s.bx) && (s.ay == s.by);
         return c;
     }
-    __device__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
-        const float2 v = xy[q];
+        const float2 v = gld(xy + q);
         x = v.x; y = v.y; id = q - c.base;
     }
     // lower side: strictly right of A->B; upper side: strictly left of A->B
     // (= strictly right of B->A). Points on the line -- A, B, duplicates and
     // collinear points -- belong to neither side.
-    __device__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
+    __device__ __forceinline__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
     {
         if (c.skip) return kNone;
-        Orient32 o;
         ++ctr.orient;
-        const int sg = orient_sign(c.ab, x, y, fp64 != 0, o, ctr.orient_exact);
-        if (sg == 0) return kNone;
+        const Orient32 o = orient32(c.ab, x, y);
+        int sg = fast_sign(o, fp64 != 0);
+        settle(sg, sg == 0, c.ab, x, y, ctr.orient_exact);
         k.a = sg < 0 ? -o.d : o.d;
         k.w = 2.0f * o.es;
-        k.x = x; k.y = y; k.id = id; k.pos = q;
-        return sg < 0 ? 0 : 1;
+        k.x = x; k.y = y; k.id = id;
+        return sg < 0 ? 0 : (sg > 0 ? 1 : kNone);
     }
-    __device__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
+    __device__ __forceinline__ int beats_fast(const Ctx&, int, const Cand& P, const Cand& Q) const
+    {
+        return sqh::beats_fast(P, Q, fp64 != 0);
+    }
+    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
         return sqh::beats(k == 0 ? c.ab : c.ba, P, Q, fp64 != 0, ctr.cmp_exact);
     }
-    __device__ Cand fetch_cand(const Ctx& c, int k, int pos, Counters&) const
+    __device__ __forceinline__ int place(const Ctx&, int, int, int) const { return 0; }
+    __device__ __forceinline__ void store(int, float, float, int) const {}
+    __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
     {
-        const float2 v = xy[pos];
-        const Orient32 o = orient32(c.ab, v.x, v.y);
-        Cand r;
-        r.a = k == 0 ? -o.d : o.d;
-        r.w = 2.0f * o.es;
-        r.x = v.x; r.y = v.y; r.id = pos - c.base; r.pos = pos;
-        return r;
-    }
-    __device__ int place(const Ctx&, int, int, int) const { return 0; }
-    __device__ void store(int, float, float, int) const {}
-    __device__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
-    {
-        SetInfo& s = sets[g];
+        SetInfo s = gld(sets + g);
         s.n_lo = a.cnt[0];
         s.n_up = a.cnt[1];
         s.clx = a.best[0].x; s.cly = a.best[0].y; s.clid = a.best[0].id;
         s.cux = a.best[1].x; s.cuy = a.best[1].y; s.cuid = a.best[1].id;
+        gst(sets + g, s);
         // vertex keys: A at the set's first slot, B right after the lower side
-        record_vertex(bitmap, vidx, c.base, s.aid);
-        if (!c.skip) record_vertex(bitmap, vidx, c.base + 1 + a.cnt[0], s.bid);
+        record_vertex(bitmap, vidx, vlist, info, c.base, s.aid);
+        if (!c.skip) record_vertex(bitmap, vidx, vlist, info, c.base + 1 + a.cnt[0], s.bid);
     }
 };
 
@@ -209,67 +213,69 @@ struct PolFirst {
     int* rec_cid;
     uint64_t* bitmap;
     int* vidx;
+    int2* vlist;
+    HullInfo* info;
     int fp64;
+    int G;
 
-    __device__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
-    __device__ int group_start(int g) const { return gstart[g]; }
-    __device__ int group_end(int g) const { return gstart[g + 1]; }
-    __device__ Ctx ctx(int g) const
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
+    __device__ __forceinline__ Ctx ctx(int g) const
     {
-        const SetInfo& s = sets[g];
+        const SetInfo s = gld(sets + g);
         Ctx c;
         c.ab = make_edge(s.ax, s.ay, s.bx, s.by);
         c.e[0] = make_edge(s.ax, s.ay, s.clx, s.cly);
         c.e[1] = make_edge(s.clx, s.cly, s.bx, s.by);
         c.e[2] = make_edge(s.bx, s.by, s.cux, s.cuy);
         c.e[3] = make_edge(s.cux, s.cuy, s.ax, s.ay);
-        c.base = gstart[g];
+        c.base = gld(gstart + g);
         c.n_lo = s.n_lo;
         c.n_up = s.n_up;
         c.skip = (s.ax == s.bx) && (s.ay == s.by);
         return c;
     }
-    __device__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
-        const float2 v = xy[q];
+        const float2 v = gld(xy + q);
         x = v.x; y = v.y; id = q - c.base;
     }
     // Section 4.4.3: a point of segment (A,B) with farthest point C is kept
     // for child (A,C) if strictly right of A->C, for child (C,B) if strictly
     // right of C->B, and discarded otherwise (inside or on triangle ACB; the
     // paper's "and" must read "or": no point is right of both lines).
-    __device__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
+    __device__ __forceinline__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
     {
         if (c.skip) return kNone;
-        Orient32 o;
-        ++ctr.orient;
-        const int side = orient_sign(c.ab, x, y, fp64 != 0, o, ctr.orient_exact);
-        if (side == 0) return kNone;
+        const bool f64 = fp64 != 0;
+        ctr.orient += 3;
+        const Orient32 o = orient32(c.ab, x, y);
+        int side = fast_sign(o, f64);
+        settle(side, side == 0, c.ab, x, y, ctr.orient_exact);
         const bool up = side > 0;
-        const Edge& E1 = up ? c.e[2] : c.e[0];
-        const Edge& E2 = up ? c.e[3] : c.e[1];
-        ++ctr.orient;
-        if (orient_sign(E1, x, y, fp64 != 0, o, ctr.orient_exact) < 0) {
-            k = make_cand(o, x, y, id, q);
-            return up ? 2 : 0;
-        }
-        ++ctr.orient;
-        if (orient_sign(E2, x, y, fp64 != 0, o, ctr.orient_exact) < 0) {
-            k = make_cand(o, x, y, id, q);
-            return up ? 3 : 1;
-        }
-        return kNone;
+        const Edge E1 = up ? c.e[2] : c.e[0];
+        const Edge E2 = up ? c.e[3] : c.e[1];
+        const Orient32 o1 = orient32(E1, x, y);
+        const Orient32 o2 = orient32(E2, x, y);
+        int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
+        settle(s1, side != 0 && s1 == 0, E1, x, y, ctr.orient_exact);
+        settle(s2, side != 0 && s1 >= 0 && s2 == 0, E2, x, y, ctr.orient_exact);
+        const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
+        k = make_cand(in1 ? o1 : o2, x, y, id);
+        const int b = up ? 2 : 0;
+        return side == 0 ? kNone : (in1 ? b : (in2 ? b + 1 : kNone));
     }
-    __device__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
+    __device__ __forceinline__ int beats_fast(const Ctx&, int, const Cand& P, const Cand& Q) const
+    {
+        return sqh::beats_fast(P, Q, fp64 != 0);
+    }
+    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
         return sqh::beats(c.e[k], P, Q, fp64 != 0, ctr.cmp_exact);
     }
-    __device__ Cand fetch_cand(const Ctx& c, int k, int pos, Counters&) const
-    {
-        const float2 v = xy[pos];
-        return make_cand(orient32(c.e[k], v.x, v.y), v.x, v.y, pos - c.base, pos);
-    }
-    __device__ int place(const Ctx& c, int, int k, int rank) const
+    __device__ __forceinline__ int place(const Ctx& c, int, int k, int rank) const
     {
         switch (k) {
         case 0: return c.base + 1 + rank;
@@ -278,29 +284,29 @@ struct PolFirst {
         default: return c.base + 1 + c.n_lo + c.n_up - rank;
         }
     }
-    __device__ void store(int dst, float x, float y, int id) const
+    __device__ __forceinline__ void store(int dst, float x, float y, int id) const
     {
-        X[dst] = x; Y[dst] = y; I[dst] = id;
+        gst(X + dst, x); gst(Y + dst, y); gst(I + dst, id);
     }
-    __device__ void child(int slot, const Edge& E, const Cand& C, int off, int len) const
+    __device__ __forceinline__ void child(int slot, const Edge& E, const Cand& C, int off, int len) const
     {
         Seg r;
         r.ax = E.ox; r.ay = E.oy; r.bx = E.ex; r.by = E.ey;
         r.cx = C.x; r.cy = C.y;
         r.off = off; r.len = len;
-        recs[slot] = r;
-        rec_cid[slot] = C.id;
+        gst(recs + slot, r);
+        gst(rec_cid + slot, C.id);
     }
-    __device__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
+    __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
     {
-        const SetInfo& s = sets[g];
+        const SetInfo s = gld(sets + g);
         if (c.n_lo > 0) {
-            record_vertex(bitmap, vidx, c.base + 1 + a.cnt[0], s.clid);
+            record_vertex(bitmap, vidx, vlist, info, c.base + 1 + a.cnt[0], s.clid);
             child(4 * g + 0, c.e[0], a.best[0], c.base + 1, a.cnt[0]);
             child(4 * g + 1, c.e[1], a.best[1], c.base + 1 + c.n_lo - a.cnt[1], a.cnt[1]);
         }
         if (c.n_up > 0) {
-            record_vertex(bitmap, vidx, c.base + 2 + c.n_lo + a.cnt[2], s.cuid);
+            record_vertex(bitmap, vidx, vlist, info, c.base + 2 + c.n_lo + a.cnt[2], s.cuid);
             child(4 * g + 2, c.e[2], a.best[2], c.base + 2 + c.n_lo, a.cnt[2]);
             child(4 * g + 3, c.e[3], a.best[3], c.base + 2 + c.n_lo + c.n_up - a.cnt[3], a.cnt[3]);
         }
@@ -333,341 +339,775 @@ struct PolPass {
     int* rec_cid;
     uint64_t* bitmap;
     int* vidx;
+    int2* vlist;
+    HullInfo* info;
     int fp64;
+    int G;
 
-    __device__ int group_of(int q, int lo, int hi) const { return search_le(vstart, q, lo, hi); }
-    __device__ int group_start(int g) const { return vstart[g]; }
-    __device__ int group_end(int g) const { return vstart[g + 1]; }
-    __device__ Ctx ctx(int g) const
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(vstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(vstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(vstart + g + 1); }
+    __device__ __forceinline__ Ctx ctx(int g) const
     {
-        const Seg s = segs[g];
+        const Seg s = gld(segs + g);
         Ctx c;
         c.e[0] = make_edge(s.ax, s.ay, s.cx, s.cy);
         c.e[1] = make_edge(s.cx, s.cy, s.bx, s.by);
         c.off = s.off;
         c.len = s.len;
-        c.vstart = vstart[g];
+        c.vstart = gld(vstart + g);
         return c;
     }
-    __device__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const int p = c.off + (q - c.vstart);
-        x = Xi[p]; y = Yi[p]; id = Ii[p];
+        x = gld(Xi + p); y = gld(Yi + p); id = gld(Ii + p);
     }
-    __device__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
+    __device__ __forceinline__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
     {
-        Orient32 o;
-        const int p = c.off + (q - c.vstart);
-        ++ctr.orient;
-        if (orient_sign(c.e[0], x, y, fp64 != 0, o, ctr.orient_exact) < 0) {
-            k = make_cand(o, x, y, id, p);
-            return 0;
-        }
-        ++ctr.orient;
-        if (orient_sign(c.e[1], x, y, fp64 != 0, o, ctr.orient_exact) < 0) {
-            k = make_cand(o, x, y, id, p);
-            return 1;
-        }
-        return kNone;
+        const bool f64 = fp64 != 0;
+        ctr.orient += 2;
+        const Orient32 o1 = orient32(c.e[0], x, y);
+        const Orient32 o2 = orient32(c.e[1], x, y);
+        int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
+        settle(s1, s1 == 0, c.e[0], x, y, ctr.orient_exact);
+        settle(s2, s1 >= 0 && s2 == 0, c.e[1], x, y, ctr.orient_exact);
+        const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
+        k = make_cand(in1 ? o1 : o2, x, y, id);
+        return in1 ? 0 : (in2 ? 1 : kNone);
     }
-    __device__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
+    __device__ __forceinline__ int beats_fast(const Ctx&, int, const Cand& P, const Cand& Q) const
+    {
+        return sqh::beats_fast(P, Q, fp64 != 0);
+    }
+    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
         return sqh::beats(c.e[k], P, Q, fp64 != 0, ctr.cmp_exact);
     }
-    __device__ Cand fetch_cand(const Ctx& c, int k, int pos, Counters&) const
-    {
-        const float x = Xi[pos], y = Yi[pos];
-        return make_cand(orient32(c.e[k], x, y), x, y, Ii[pos], pos);
-    }
-    __device__ int place(const Ctx& c, int, int k, int rank) const
+    __device__ __forceinline__ int place(const Ctx& c, int, int k, int rank) const
     {
         return k == 0 ? c.off + rank : c.off + c.len - 1 - rank;
     }
-    __device__ void store(int dst, float x, float y, int id) const
+    __device__ __forceinline__ void store(int dst, float x, float y, int id) const
     {
-        Xo[dst] = x; Yo[dst] = y; Io[dst] = id;
+        gst(Xo + dst, x); gst(Yo + dst, y); gst(Io + dst, id);
     }
-    __device__ void child(int slot, const Edge& E, const Cand& C, int off, int len) const
+    __device__ __forceinline__ void child(int slot, const Edge& E, const Cand& C, int off, int len) const
     {
         Seg r;
         r.ax = E.ox; r.ay = E.oy; r.bx = E.ex; r.by = E.ey;
         r.cx = C.x; r.cy = C.y;
         r.off = off; r.len = len;
-        recs[slot] = r;
-        rec_cid[slot] = C.id;
+        gst(recs + slot, r);
+        gst(rec_cid + slot, C.id);
     }
-    __device__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
+    __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
     {
-        record_vertex(bitmap, vidx, c.off + a.cnt[0], seg_cid[g]);
+        record_vertex(bitmap, vidx, vlist, info, c.off + a.cnt[0], gld(seg_cid + g));
         child(2 * g + 0, c.e[0], a.best[0], c.off, a.cnt[0]);
         child(2 * g + 1, c.e[1], a.best[1], c.off + c.len - a.cnt[1], a.cnt[1]);
     }
 };
 
-template <class Pol>
-__global__ __launch_bounds__(kBlock) void k_tiles(Pol pol, const int* Pp, int Pc, const int* Gp, int Gc,
-                                                  int nt_cap, uint64_t* lb, int* err, uint32_t* stats)
+// ================================================== persistent hull kernel ==
+//
+// One cooperative launch computes all hulls of a call: seed, first split,
+// first compaction, the segmented passes until no segment has points, and
+// the ordered emission. One 1024-thread workgroup runs per compute unit;
+// workgroups meet at grid barriers between steps. Loop bounds are read by
+// every workgroup after a barrier, so all of them take the same path. Once
+// few points are left, workgroup 0 finishes the remaining passes alone
+// (no grid barriers).
+
+// Grid barrier. Arrival counters are split over kBarSub sub-counters to cut
+// same-address atomic serialisation; each workgroup issues one release fence
+// before arriving and one acquire fence after leaving, and spins with
+// relaxed loads. The last arriver of a sub-counter acquires (so later
+// arrivals carry the earlier ones' writes) before arriving at the top
+// counter; the last top arriver publishes the new generation with a release
+// store. Bounded spin: on timeout the error flag is raised and the
+// workgroup continues.
+constexpr int kBarSub = 16;
+struct GridBar {
+    unsigned int gen;
+    unsigned int top;
+    unsigned int pad[14];
+    unsigned int sub[kBarSub][16];  // one 64-byte line per sub-counter
+    unsigned int emit_mode;         // broadcast from workgroup 0 (see k_hull)
+    unsigned int pad2[15];
+};
+
+__device__ __forceinline__ void spin_gen(GridBar* bar, unsigned int g, int* err)
 {
-    __shared__ TileShared<Pol> sh;
-    const int P = Pp ? *Pp : Pc;
-    const int G = Gp ? *Gp : Gc;
-    constexpr int T = Pol::ROWS * 64 * kWaves;
-    const int nt = (P + T - 1) / T;
-    if (nt > nt_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, kErrBounds);
-        return;
+    int spins = 0;
+    while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > kSpinLimit) {
+            atomicOr(err, kErrSpin);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
     }
-    Counters ctr = {0u, 0u, 0u};
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) process_tile(pol, t, P, G, lb, err, sh, ctr);
-    flush_counters(stats, ctr);
 }
 
-template __global__ void k_tiles<PolSeed>(PolSeed, const int*, int, const int*, int, int, uint64_t*, int*, uint32_t*);
-template __global__ void k_tiles<PolSplit>(PolSplit, const int*, int, const int*, int, int, uint64_t*, int*, uint32_t*);
-template __global__ void k_tiles<PolFirst>(PolFirst, const int*, int, const int*, int, int, uint64_t*, int*, uint32_t*);
-template __global__ void k_tiles<PolPass>(PolPass, const int*, int, const int*, int, int, uint64_t*, int*, uint32_t*);
+__device__ __forceinline__ void grid_sync(GridBar* bar, int* err)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int nb = gridDim.x, i = blockIdx.x % kBarSub;
+        const unsigned int nsub = (nb - i + kBarSub - 1) / kBarSub;
+        const unsigned int ntop = nb < (unsigned)kBarSub ? nb : (unsigned)kBarSub;
+        const unsigned int g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int a = __hip_atomic_fetch_add(&bar->sub[i][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == nsub - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(&bar->sub[i][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int t = __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ntop - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&bar->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                spin_gen(bar, g, err);
+            }
+        } else {
+            spin_gen(bar, g, err);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
 
-// ================================================== ordered scans ==
-// Exclusive scan of (a, b) pairs over items with one-word decoupled look-back
-// (no groups). Used to rebuild the segment table and to rank hull vertices.
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kBlock * kScanItems;
+__device__ __forceinline__ int ld_flag(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 struct Pair {
     int a, b;
 };
 
-__device__ __forceinline__ Pair wave_incl_scan(Pair v)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int oa = __shfl_up(v.a, d), ob = __shfl_up(v.b, d);
-        if (lane >= d) { v.a += oa; v.b += ob; }
-    }
-    return v;
-}
-
-// Block-wide exclusive scan of one pair per thread; returns the block total
-// in *tot. Uses sh[kWaves].
-__device__ __forceinline__ Pair block_excl_scan(Pair v, Pair* sh, Pair* tot)
+// Block-wide exclusive scan of one pair per thread; *tot receives the block
+// total. `red` holds kWaves pairs.
+__device__ __forceinline__ Pair block_excl_scan(Pair v, Pair* red, Pair* tot)
 {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
-    const Pair inc = wave_incl_scan(v);
-    if (lane == 63) sh[w] = inc;
+    Pair inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int oa = __shfl_up(inc.a, d), ob = __shfl_up(inc.b, d);
+        if (lane >= d) { inc.a += oa; inc.b += ob; }
+    }
+    __syncthreads();
+    if (lane == 63) red[w] = inc;
     __syncthreads();
     Pair off = {0, 0}, all = {0, 0};
 #pragma unroll
     for (int u = 0; u < kWaves; ++u) {
-        if (u < w) { off.a += sh[u].a; off.b += sh[u].b; }
-        all.a += sh[u].a; all.b += sh[u].b;
+        if (u < w) { off.a += red[u].a; off.b += red[u].b; }
+        all.a += red[u].a; all.b += red[u].b;
     }
     *tot = all;
-    __syncthreads();
     return Pair{off.a + inc.a - v.a, off.b + inc.b - v.b};
 }
 
-// prefix of tile t's predecessors (window look-back by one wave)
-__device__ Pair scan_look_back(const uint64_t* lb, int t, int* err)
+constexpr int kMaxChunks = 512;  // workgroups of the persistent grid (upper bound)
+constexpr int kMaxInfoPasses = 256;
+constexpr int kMaxPasses = 1 << 16;
+constexpr int kMaxStamps = 1024;
+constexpr int kTailPoints = 1 << 16;   // below this many points one workgroup finishes the passes
+constexpr int kSmallHull = 2048;       // single hulls up to this size are emitted by one workgroup
+
+// info block written for the host
+struct HullInfo {
+    int h_total;
+    int passes;
+    int first_v;
+    int vcount;
+    int vcap;     // capacity of the vertex list
+    int pass_s[kMaxInfoPasses];
+    int pass_v[kMaxInfoPasses];
+    int nstamps;
+    int stamp_tag[kMaxStamps];
+    unsigned long long stamp[kMaxStamps];
+    unsigned long long trace[kMaxChunks][8];  // per-workgroup timestamps (timing == 2)
+};
+
+struct HullArgs {
+    const float2* xy;
+    int N, G;
+    const int64_t* set_off;  // device, G + 1 (null: one set [0, N))
+    int32_t* out;
+    int64_t cap;
+    int64_t* out_off;        // device, G + 1 (null for a single hull)
+    float* X[2];
+    float* Y[2];
+    int* I[2];
+    int* gstart;
+    SetInfo* sets;
+    Seg* recs;
+    int* rec_cid;
+    Seg* segs[2];
+    int* seg_cid[2];
+    int* vstart[2];
+    int* sv;                 // {S0, V0, S1, V1}
+    uint64_t* bitmap;
+    int* vidx;
+    int2* vlist;             // (key, id) of recorded vertices, first kVListCap
+    int* wprefix;
+    int W;
+    void* slots;             // ChunkSlot<4>[gridDim.x]
+    Pair* ctab;              // per-workgroup pairs (emission)
+    GridBar* bar;
+    int* err;
+    uint32_t* stats;
+    HullInfo* info;
+    int fp64;
+    int timing;
+    int vcap;
+};
+
+__device__ __forceinline__ void stamp(const HullArgs& a, int tag)
 {
-    const int lane = lane_id();
-    Pair acc = {0, 0};
-    int base = t - 1, spins = 0;
-    while (true) {
-        const int j = base - lane;
-        uint64_t wv = 0;
-        bool inc_ok = false, agg_ok = false;
-        if (j >= 0) {
-            wv = ld_word(lb + 2 * (size_t)j + 1);
-            inc_ok = word_ok(wv);
-            if (!inc_ok) {
-                wv = ld_word(lb + 2 * (size_t)j);
-                agg_ok = word_ok(wv);
-            }
+    if (a.timing && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int k = a.info->nstamps;
+        if (k < kMaxStamps) {
+            a.info->stamp[k] = wall_clock64();
+            a.info->stamp_tag[k] = tag;
+            a.info->nstamps = k + 1;
         }
-        const uint64_t incm = __ballot(inc_ok);
-        const uint64_t rdym = __ballot(inc_ok || agg_ok || j < 0);
-        const int first_inc = incm ? (__ffsll((unsigned long long)incm) - 1) : 64;
-        const uint64_t need = first_inc < 64 ? mask_le(first_inc) : ~0ull;
-        if ((rdym & need) != need) {
-            if (++spins > kSpinLimit) {
-                if (lane == 0) atomicOr(err, kErrSpin);
-                return acc;
-            }
-            __builtin_amdgcn_s_sleep(2);
-            continue;
-        }
-        int a = 0, b = 0;
-        if (lane <= first_inc && j >= 0) { a = (int)word_hi(wv); b = (int)word_lo(wv); }
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) { a += __shfl_xor(a, m); b += __shfl_xor(b, m); }
-        acc.a += a; acc.b += b;
-        if (first_inc < 64 || base - 63 <= 0) break;
-        base -= 64;
     }
-    return acc;
 }
 
-// Tile prefix with publication; all threads get the result.
-__device__ __forceinline__ Pair tile_prefix(uint64_t* lb, int t, Pair tot, Pair* shp, int* err)
+__device__ __forceinline__ void trace(const HullArgs& a, int slot)
 {
-    if (threadIdx.x < 64) {
-        Pair pre = {0, 0};
-        if (t == 0) {
-            if (threadIdx.x == 0) st_word(lb + 1, pack2(tot.a, tot.b));
+    if (a.timing == 2 && threadIdx.x == 0 && blockIdx.x < kMaxChunks) a.info->trace[blockIdx.x][slot] = wall_clock64();
+}
+
+__device__ __forceinline__ int chunk_len(int P, int nb)
+{
+    int ch = (P + nb - 1) / nb;
+    ch = (ch + 63) & ~63;
+    return ch < 64 ? 64 : ch;
+}
+
+// Chunk summaries for step BC: for chunk b, the count prefix of its first
+// group from the chunks before it, and the running position in the next
+// segment table (active child segments and their points finalised by chunks
+// < b, and by chunk b itself). One thread per chunk, a segmented
+// Hillis-Steele scan in LDS over the running group's counts.
+template <int NB>
+struct ScanOut {
+    int prefix[NB];
+    Pair tab_before;
+    Pair tab_self;
+};
+
+template <int NB>
+struct ScanLds {
+    int cont[kMaxChunks];        // chunk continues the running group of chunk - 1
+    int run[2][kMaxChunks][NB];  // running counts (double-buffered scan)
+    int tab_a[kMaxChunks], tab_b[kMaxChunks];
+};
+
+// LDS of slot_scan, shared by all phases
+__shared__ int g_summ[sizeof(ScanLds<4>) / sizeof(int)];
+
+template <class Pol>
+__device__ __forceinline__ void slot_scan(const ChunkSlot<Pol::NB>* slots, int b, int nonempty, ScanLds<Pol::NB>& L,
+                                          ScanOut<Pol::NB>& o, Pair* red)
+{
+    constexpr int NB = Pol::NB;
+    const int n = min(b + 1, nonempty);  // chunks 0..n-1
+    const int t = (int)threadIdx.x;
+    int first_cnt[NB];
+    bool before = false, done = false, head = true;
+    if (t < n) {
+        const int lg = gld(&slots[t].last_g), fg = gld(&slots[t].first_g);
+        before = gld(&slots[t].first_before) != 0;
+        done = gld(&slots[t].first_done) != 0;
+        const int prev_lg = t > 0 ? gld(&slots[t - 1].last_g) : -1;
+        // chunk t lies inside the group running out of chunk t-1
+        head = !(before && !done && lg == fg && fg == prev_lg);
+        L.cont[t] = head ? 0 : 1;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            L.run[0][t][k] = gld(&slots[t].last.cnt[k]);
+            first_cnt[k] = gld(&slots[t].first.cnt[k]);
+        }
+        L.tab_a[t] = gld(&slots[t].tab_a);
+        L.tab_b[t] = gld(&slots[t].tab_b);
+    }
+    __syncthreads();
+    // segmented inclusive scan: run[t] = counts of the group running out of
+    // chunk t, accumulated since the chunk where it started
+    int src = 0;
+    int hd = (t < n) ? (head ? 1 : 0) : 1;  // a segment head lies within the window ending at t
+    for (int d = 1; d < n; d <<= 1) {
+        int v[NB];
+        int nh = hd;
+        if (t < n) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) v[k] = L.run[src][t][k];
+            if (!hd && t >= d) {
+#pragma unroll
+                for (int k = 0; k < NB; ++k) v[k] += L.run[src][t - d][k];
+                nh = L.cont[t - d] ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        if (t < n) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) L.run[src ^ 1][t][k] = v[k];
+            L.cont[t] = nh ? 0 : 1;
+        }
+        __syncthreads();
+        hd = nh;
+        src ^= 1;
+    }
+    // per chunk: table contribution, including the group that runs into it and ends inside
+    Pair tab = {0, 0};
+    int pre[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pre[k] = 0;
+    if (t < n) {
+        tab.a = L.tab_a[t];
+        tab.b = L.tab_b[t];
+        if (t > 0 && before) {
+            const int fg = gld(&slots[t].first_g);
+            if (fg == gld(&slots[t - 1].last_g)) {
+#pragma unroll
+                for (int k = 0; k < NB; ++k) pre[k] = L.run[src][t - 1][k];
+            }
+        }
+        if (done) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int tot = pre[k] + first_cnt[k];
+                if (tot > 0) { tab.a += 1; tab.b += tot; }
+            }
+        }
+    }
+    if (t == b) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) o.prefix[k] = pre[k];
+        o.tab_self = tab;
+    }
+    Pair total;
+    const Pair ex = block_excl_scan(tab, red, &total);
+    if (t == b || (t == n - 1 && b >= n)) {
+        o.tab_before = ex;
+        if (b >= n) o.tab_self = tab;
+    }
+    __syncthreads();
+}
+
+// Step A of a phase over [0, P) split into nb chunks; publishes slot b.
+// mul > 0: child records recs[mul*g + k] of groups finalised here are counted.
+template <class Pol>
+__device__ __forceinline__ void phase_step_a(const HullArgs& a, const Pol& pol, int P, int nb, int b, int mul,
+                                             ChunkShared<Pol>& sh, Pair* red, Counters& ctr, int& glo, int& ghi)
+{
+    auto* slots = reinterpret_cast<ChunkSlot<Pol::NB>*>(a.slots);
+    const int CH = chunk_len(P, nb);
+    const int cb = (int)min((long long)b * CH, (long long)P), ce = min(cb + CH, P);
+    const int G = pol.num_groups();
+    glo = 0;
+    ghi = -1;
+    if (threadIdx.x == 0) {
+        sh.carry_g = -1;
+        agg_clear(sh.carry);
+        sh.first_done = 0;
+    }
+    __syncthreads();
+    if (cb >= ce) return;
+    glo = pol.group_of(cb, 0, G - 1);
+    ghi = pol.group_of(ce - 1, glo, G - 1);
+    process_chunk<Pol, kModeAgg>(pol, cb, ce, glo, ghi, sh, ctr);
+    Pair tab = {0, 0};
+    if (mul > 0) {
+        // groups that start and end inside the chunk were finalised in this step
+        const int ga = pol.group_start(glo) >= cb ? glo : glo + 1;
+        const int gb = pol.group_end(ghi) <= ce ? ghi : ghi - 1;
+        Pair mine = {0, 0};
+        for (int i = mul * ga + (int)threadIdx.x; i < mul * (gb + 1); i += kBlock) {
+            const int len = gld(&a.recs[i].len);
+            if (len > 0) { mine.a += 1; mine.b += len; }
+        }
+        block_excl_scan(mine, red, &tab);
+    }
+    if (threadIdx.x == 0) {
+        ChunkSlot<Pol::NB> s;
+        s.last_g = sh.carry_g;
+        s.first_g = glo;
+        s.first_before = pol.group_start(glo) < cb;
+        s.first_done = sh.first_done;
+        s.tab_a = tab.a;
+        s.tab_b = tab.b;
+        s.last = sh.carry;
+        s.first = sh.first_total;
+        s.pad[0] = s.pad[1] = 0;
+        gst(slots + b, s);
+    }
+}
+
+// Step B of a reduction phase: finalise the chunk's first group if it ends
+// here (prefix from the chunks before).
+template <class Pol>
+__device__ __forceinline__ void phase_step_b(const HullArgs& a, const Pol& pol, int P, int nb, int b,
+                                             ChunkShared<Pol>& sh, Counters& ctr)
+{
+    auto* slots = reinterpret_cast<ChunkSlot<Pol::NB>*>(a.slots);
+    const int CH = chunk_len(P, nb);
+    const int cb = (int)min((long long)b * CH, (long long)P), ce = min(cb + CH, P);
+    if (cb >= ce) return;
+    chunk_first_group(pol, b, cb, CH, slots, nullptr, sh, ctr);
+}
+
+// Steps B and C of a compaction phase: finalise the chunk's first group if
+// it ends here, compact the child records of the groups finalised by this
+// chunk into the next segment table, then write the chunk's points to their
+// child segments.
+template <class Pol>
+__device__ __forceinline__ void phase_step_bc(const HullArgs& a, const Pol& pol, int P, int nb, int b, int mul,
+                                              int glo, int ghi, Seg* segs, int* seg_cid, int* vstart, int* sv,
+                                              ChunkShared<Pol>& sh, Pair* red, Counters& ctr)
+{
+    auto* slots = reinterpret_cast<ChunkSlot<Pol::NB>*>(a.slots);
+    const int CH = chunk_len(P, nb);
+    const int cb = (int)min((long long)b * CH, (long long)P), ce = min(cb + CH, P);
+    const int nonempty = (P + CH - 1) / CH;
+    __shared__ ScanOut<Pol::NB> so;
+    slot_scan<Pol>(slots, b, nonempty, *reinterpret_cast<ScanLds<Pol::NB>*>(g_summ), so, red);
+    Pair at = so.tab_before;
+    if (b >= nonempty) {
+        // empty chunk: only the last workgroup has a job, the table totals
+        if (b == nb - 1 && threadIdx.x == 0) {
+            const Pair tot = {so.tab_before.a + so.tab_self.a, so.tab_before.b + so.tab_self.b};
+            sv[0] = tot.a;
+            sv[1] = tot.b;
+            vstart[tot.a] = tot.b;
+        }
+        return;
+    }
+    chunk_first_group(pol, b, cb, CH, slots, so.prefix, sh, ctr);
+    // records of the groups finalised by this chunk
+    const int ga = (pol.group_start(glo) >= cb || sh.first_done) ? glo : glo + 1;
+    const int gb = pol.group_end(ghi) <= ce ? ghi : ghi - 1;
+    for (int i0 = mul * ga; i0 < mul * (gb + 1); i0 += kBlock) {
+        const int i = i0 + (int)threadIdx.x;
+        Seg r;
+        r.len = 0;
+        if (i < mul * (gb + 1)) r = gld(a.recs + i);
+        const Pair v = {r.len > 0 ? 1 : 0, r.len > 0 ? r.len : 0};
+        Pair tot;
+        const Pair ex = block_excl_scan(v, red, &tot);
+        if (r.len > 0) {
+            const int pos = at.a + ex.a;
+            gst(segs + pos, r);
+            gst(seg_cid + pos, gld(a.rec_cid + i));
+            gst(vstart + pos, at.b + ex.b);
+        }
+        at.a += tot.a;
+        at.b += tot.b;
+        __syncthreads();
+    }
+    if (b == nb - 1 && threadIdx.x == 0) {
+        sv[0] = at.a;
+        sv[1] = at.b;
+        vstart[at.a] = at.b;
+    }
+    process_chunk<Pol, kModeScatter>(pol, cb, ce, glo, ghi, sh, ctr);
+}
+
+// A reduction phase on the whole grid.
+template <class Pol>
+__device__ __forceinline__ void phase_reduce(const HullArgs& a, const Pol& pol, int P, ChunkShared<Pol>& sh,
+                                             Pair* red, Counters& ctr)
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    int glo, ghi;
+    const int t0 = Pol::COUNTS ? 4 : 0;
+    trace(a, t0 + 0);
+    phase_step_a(a, pol, P, nb, b, 0, sh, red, ctr, glo, ghi);
+    trace(a, t0 + 1);
+    grid_sync(a.bar, a.err);
+    trace(a, t0 + 2);
+    phase_step_b(a, pol, P, nb, b, sh, ctr);
+    trace(a, t0 + 3);
+    grid_sync(a.bar, a.err);
+}
+
+// A compaction phase: on the whole grid, or (SINGLE) on workgroup 0 alone.
+template <class Pol, bool SINGLE>
+__device__ __forceinline__ void phase_compact(const HullArgs& a, const Pol& pol, int P, int mul, Seg* segs,
+                                              int* seg_cid, int* vstart, int* sv, ChunkShared<Pol>& sh, Pair* red,
+                                              Counters& ctr)
+{
+    const int nb = SINGLE ? 1 : (int)gridDim.x, b = SINGLE ? 0 : (int)blockIdx.x;
+    int glo, ghi;
+    phase_step_a(a, pol, P, nb, b, mul, sh, red, ctr, glo, ghi);
+    if (SINGLE) __syncthreads();
+    else grid_sync(a.bar, a.err);
+    phase_step_bc(a, pol, P, nb, b, mul, glo, ghi, segs, seg_cid, vstart, sv, sh, red, ctr);
+    if (SINGLE) __syncthreads();
+    else grid_sync(a.bar, a.err);
+}
+
+template <class Pol, bool SINGLE>
+__device__ __forceinline__ void run_pass(const HullArgs& a, int cur, int S, int V, ChunkShared<PolPass>& sh,
+                                         Pair* red, Counters& ctr)
+{
+    const int nxt = cur ^ 1;
+    PolPass pol{a.segs[cur], a.seg_cid[cur], a.vstart[cur], a.X[cur], a.Y[cur], a.I[cur], a.X[nxt], a.Y[nxt],
+                a.I[nxt], a.recs, a.rec_cid, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, S};
+    phase_compact<PolPass, SINGLE>(a, pol, V, 2, a.segs[nxt], a.seg_cid[nxt], a.vstart[nxt], a.sv + 2 * nxt, sh, red,
+                                   ctr);
+}
+
+__device__ __forceinline__ void note_pass(const HullArgs& a, int pass, int S, int V)
+{
+    if (threadIdx.x == 0) {
+        if (pass == 0) a.info->first_v = V;
+        if (pass < kMaxInfoPasses) { a.info->pass_s[pass] = S; a.info->pass_v[pass] = V; }
+        a.info->passes = pass;
+    }
+}
+
+// Ordered emission of a single hull with few vertices by one workgroup: the
+// rank of a vertex is the number of vertices with a smaller key.
+__device__ __forceinline__ void emit_small(const HullArgs& a, int h, int2* lds)
+{
+    for (int i = (int)threadIdx.x; i < h; i += kBlock) lds[i] = gld(a.vlist + i);
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < h; i += kBlock) {
+        const int key = lds[i].x;
+        int rank = 0;
+        for (int j = 0; j < h; ++j) rank += lds[j].x < key;
+        if (rank < a.cap) gst(a.out + rank, lds[i].y);
+    }
+    if (threadIdx.x == 0) a.info->h_total = h;
+    __syncthreads();
+}
+
+// Ordered emission on the whole grid: vertex keys are the set bits of the
+// bitmap; the rank of a key among all keys is its output position (keys
+// increase along each set's ring and sets are stored in order).
+__device__ __forceinline__ void emit_grid(const HullArgs& a, Pair* red)
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int gtid = b * kBlock + (int)threadIdx.x, gstride = nb * kBlock;
+    const int W = a.W;
+    const int CHw = (W + nb - 1) / nb;
+    const int wb = min(b * CHw, W), we = min(wb + CHw, W);
+    Pair mine = {0, 0};
+    for (int i = wb + (int)threadIdx.x; i < we; i += kBlock) mine.a += __popcll(gld(a.bitmap + i));
+    Pair tot;
+    block_excl_scan(mine, red, &tot);
+    if (threadIdx.x == 0) a.ctab[b] = tot;
+    grid_sync(a.bar, a.err);
+    Pair pre = {0, 0};
+    for (int c = (int)threadIdx.x; c < b; c += kBlock) pre.a += gld(&a.ctab[c].a);
+    Pair ptot;
+    block_excl_scan(pre, red, &ptot);
+    int at = ptot.a;
+    __syncthreads();
+    for (int i0 = wb; i0 < we; i0 += kBlock) {
+        const int i = i0 + (int)threadIdx.x;
+        const uint64_t word = i < we ? gld(a.bitmap + i) : 0ull;
+        Pair t;
+        const Pair ex = block_excl_scan(Pair{(int)__popcll(word), 0}, red, &t);
+        if (i < we) {
+            int rank = at + ex.a;
+            gst(a.wprefix + i, rank);
+            uint64_t bits = word;
+            while (bits) {
+                const int bit = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1;
+                if (rank < a.cap) gst(a.out + rank, gld(a.vidx + i * 64 + bit));
+                ++rank;
+            }
+        }
+        at += t.a;
+        __syncthreads();
+    }
+    if (b == nb - 1 && threadIdx.x == 0) a.info->h_total = at;
+    if (a.out_off) {
+        grid_sync(a.bar, a.err);
+        const int h = ld_flag(&a.info->h_total);
+        for (int s = gtid; s <= a.G; s += gstride) {
+            const int key = a.gstart[s];
+            int64_t v;
+            if (key >= a.N) v = h;
+            else v = a.wprefix[key >> 6] + __popcll(a.bitmap[key >> 6] & mask_lt(key & 63));
+            a.out_off[s] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
+{
+    __shared__ ChunkShared<PolFirst> sh_first;
+    __shared__ Pair red[kWaves];
+    __shared__ int2 vl[kSmallHull];
+    auto& shF = sh_first;
+    auto& shS = *reinterpret_cast<ChunkShared<PolSeed>*>(&sh_first);
+    auto& shP = *reinterpret_cast<ChunkShared<PolSplit>*>(&sh_first);
+    auto& shQ = *reinterpret_cast<ChunkShared<PolPass>*>(&sh_first);
+    Counters ctr = {0u, 0u, 0u};
+    const int b = (int)blockIdx.x;
+    bool tail = false;
+
+    stamp(a, 0);
+    if (ld_flag(a.err) & kErrBounds) goto done;  // set offsets rejected by k_reset
+    // ---- seed: lexmin / lexmax of every set
+    {
+        PolSeed pol{a.xy, a.gstart, a.sets, a.err, a.G};
+        phase_reduce(a, pol, a.N, shS, red, ctr);
+    }
+    stamp(a, 1);
+    // flags raised before the barrier decide the path; every workgroup sees them
+    if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;
+    // ---- first split: side counts and farthest point of each side
+    {
+        PolSplit pol{a.xy, a.gstart, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, a.G};
+        phase_reduce(a, pol, a.N, shP, red, ctr);
+    }
+    stamp(a, 2);
+    // ---- first compaction into four child segments per set
+    {
+        PolFirst pol{a.xy, a.gstart, a.sets, a.X[0], a.Y[0], a.I[0], a.recs, a.rec_cid, a.bitmap, a.vidx,
+                     a.vlist, a.info, a.fp64, a.G};
+        phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, shF, red, ctr);
+    }
+    stamp(a, 3);
+    // ---- segmented passes over all segments of all sets
+    {
+        int cur = 0;
+        for (int pass = 0;; ++pass) {
+            const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
+            if (b == 0) note_pass(a, pass, S, V);
+            if (S <= 0) break;
+            if (pass >= kMaxPasses) {  // pass limit: report and stop
+                if (b == 0 && threadIdx.x == 0) atomicOr(a.err, kErrBounds);
+                break;
+            }
+            if (V <= kTailPoints) {
+                // few points left: workgroup 0 finishes the passes alone
+                tail = true;
+                if (b == 0) {
+                    for (int p = pass;; ++p) {
+                        const int S2 = ld_flag(a.sv + 2 * cur), V2 = ld_flag(a.sv + 2 * cur + 1);
+                        note_pass(a, p, S2, V2);
+                        if (S2 <= 0) break;
+                        if (p >= kMaxPasses) {
+                            if (threadIdx.x == 0) atomicOr(a.err, kErrBounds);
+                            break;
+                        }
+                        run_pass<PolPass, true>(a, cur, S2, V2, shQ, red, ctr);
+                        stamp(a, 100 + p);
+                        cur ^= 1;
+                    }
+                }
+                break;
+            }
+            run_pass<PolPass, false>(a, cur, S, V, shQ, red, ctr);
+            stamp(a, 100 + pass);
+            cur ^= 1;
+        }
+    }
+    // ---- ordered emission
+    {
+        // workgroup 0 decides: one workgroup (single hull, few vertices) or the grid
+        unsigned int mode;
+        if (b == 0) {
+            const int h = ld_flag(&a.info->vcount);
+            mode = (a.G == 1 && h <= kSmallHull && h <= a.vcap) ? 1u : 2u;
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(&a.bar->emit_mode, mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (mode == 1u) emit_small(a, h, vl);
+        } else if (tail) {
+            // wait for workgroup 0's decision (it is still running the last passes)
+            __shared__ unsigned int smode;
+            if (threadIdx.x == 0) {
+                int spins = 0;
+                unsigned int m;
+                while ((m = __hip_atomic_load(&a.bar->emit_mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, kErrSpin);
+                        m = 1u;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                smode = m;
+            }
+            __syncthreads();
+            mode = smode;
         } else {
-            if (threadIdx.x == 0) st_word(lb + 2 * (size_t)t, pack2(tot.a, tot.b));
-            pre = scan_look_back(lb, t, err);
-            if (threadIdx.x == 0) st_word(lb + 2 * (size_t)t + 1, pack2(pre.a + tot.a, pre.b + tot.b));
+            // the pass loop ended on a grid barrier: every workgroup can decide
+            const int h = ld_flag(&a.info->vcount);
+            mode = (a.G == 1 && h <= kSmallHull && h <= a.vcap) ? 1u : 2u;
         }
-        if (threadIdx.x == 0) *shp = pre;
+        if (mode == 2u) emit_grid(a, red);
     }
-    __syncthreads();
-    const Pair r = *shp;
-    __syncthreads();
-    return r;
+    stamp(a, 4);
+done:
+    flush_counters(a.stats, ctr);
 }
 
-// Segment-table rebuild: the child records recs[0..M) (M = mul * *nprev, or
-// Mc if nprev is null) in ring order; active ones (len > 0) are compacted
-// into segs with vstart = running sum of len. out_sv = {S, V}.
-__global__ __launch_bounds__(kBlock) void k_table(const Seg* recs, const int* rec_cid, const int* nprev, int mul,
-                                                  int Mc, Seg* segs, int* seg_cid, int* vstart, int* out_sv,
-                                                  int nt_cap, uint64_t* lb, int* err)
+// Per-call initialisation (a normal launch before k_hull): barrier state,
+// error word, counters, info block, the vertex bitmap, the first child
+// records, and the set starts (validated).
+__global__ void k_reset(HullArgs a)
 {
-    __shared__ Pair shw[kWaves];
-    __shared__ Pair shp;
-    const int M = nprev ? mul * (*nprev) : Mc;
-    const int nt = (M + kScanTile - 1) / kScanTile;
-    if (nt > nt_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, kErrBounds);
-        return;
+    const int gtid = (int)(blockIdx.x * blockDim.x + threadIdx.x), gstride = (int)(gridDim.x * blockDim.x);
+    if (gtid == 0) {
+        a.bar->gen = 0;
+        a.bar->top = 0;
+        a.bar->emit_mode = 0;
+        *a.err = 0;
+        a.info->h_total = 0;
+        a.info->passes = 0;
+        a.info->nstamps = 0;
+        a.info->first_v = 0;
+        a.info->vcount = 0;
+        a.info->vcap = a.vcap;
     }
-    if (M == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) { out_sv[0] = 0; out_sv[1] = 0; vstart[0] = 0; }
-        return;
+    if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
+    for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;
+    for (int i = gtid; i < a.W; i += gstride) a.bitmap[i] = 0ull;
+    for (int i = gtid; i < 4 * a.G; i += gstride) {
+        a.recs[i].len = 0;
+        a.rec_cid[i] = -1;
     }
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-        const int i0 = t * kScanTile + (int)threadIdx.x * kScanItems;
-        Pair mine = {0, 0};
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int i = i0 + k;
-            if (i < M) {
-                const int len = recs[i].len;
-                if (len > 0) { mine.a += 1; mine.b += len; }
-            }
+    if (a.set_off) {
+        for (int s = gtid; s <= a.G; s += gstride) {
+            const int64_t v = a.set_off[s];
+            bool bad = v < 0 || v > a.N;
+            if (s == 0 && v != 0) bad = true;
+            if (s == a.G && v != a.N) bad = true;
+            if (s > 0 && a.set_off[s - 1] > v) bad = true;
+            if (bad) atomicOr(a.err, kErrBounds);
+            a.gstart[s] = bad ? 0 : (int)v;
         }
-        Pair tot;
-        const Pair ex = block_excl_scan(mine, shw, &tot);
-        const Pair pre = tile_prefix(lb, t, tot, &shp, err);
-        Pair at = {pre.a + ex.a, pre.b + ex.b};
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int i = i0 + k;
-            if (i < M) {
-                const Seg r = recs[i];
-                if (r.len > 0) {
-                    segs[at.a] = r;
-                    seg_cid[at.a] = rec_cid[i];
-                    vstart[at.a] = at.b;
-                    at.a += 1;
-                    at.b += r.len;
-                }
-            }
-        }
-        if (t == nt - 1 && threadIdx.x == 0) {
-            out_sv[0] = pre.a + tot.a;
-            out_sv[1] = pre.b + tot.b;
-            vstart[pre.a + tot.a] = pre.b + tot.b;
-        }
+    } else if (gtid == 0) {
+        a.gstart[0] = 0;
+        a.gstart[1] = a.N;
     }
 }
 
-// Ordered emission: vertex keys are the set bits of bitmap[0..W); the rank of
-// a key among all set bits is its output position (keys increase along each
-// set's ring and sets are stored in order). wprefix[w] = set bits before word w.
-__global__ __launch_bounds__(kBlock) void k_emit(const uint64_t* bitmap, const int* vidx, int W, int32_t* out,
-                                                 int64_t cap, int* wprefix, int* total, int nt_cap, uint64_t* lb,
-                                                 int* err)
+}  // namespace sqh
+
+namespace sqh {
+// Vertex list for the small-hull emission (first kVListCap vertices).
+__device__ __forceinline__ void note_vertex(HullInfo* info, int2* vlist, int key, int id)
 {
-    __shared__ Pair shw[kWaves];
-    __shared__ Pair shp;
-    const int nt = (W + kScanTile - 1) / kScanTile;
-    if (nt > nt_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, kErrBounds);
-        return;
-    }
-    if (W == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *total = 0;
-        return;
-    }
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-        const int i0 = t * kScanTile + (int)threadIdx.x * kScanItems;
-        uint64_t wd[kScanItems];
-        Pair mine = {0, 0};
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int i = i0 + k;
-            wd[k] = i < W ? bitmap[i] : 0ull;
-            mine.a += __popcll(wd[k]);
-        }
-        Pair tot;
-        const Pair ex = block_excl_scan(mine, shw, &tot);
-        const Pair pre = tile_prefix(lb, t, tot, &shp, err);
-        int rank = pre.a + ex.a;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int i = i0 + k;
-            if (i < W) {
-                wprefix[i] = rank;
-                uint64_t bits = wd[k];
-                while (bits) {
-                    const int b = __ffsll((unsigned long long)bits) - 1;
-                    bits &= bits - 1;
-                    if (rank < cap) out[rank] = vidx[i * 64 + b];
-                    ++rank;
-                }
-            }
-        }
-        if (t == nt - 1 && threadIdx.x == 0) *total = pre.a + tot.a;
-    }
+    const int i = atomicAdd(&info->vcount, 1);
+    if (i < info->vcap) vlist[i] = make_int2(key, id);
 }
-
-// Output offsets of a batch: out_off[s] = vertices with key < set_off[s].
-__global__ void k_out_offsets(const int* gstart, int nsets, int N, const uint64_t* bitmap, const int* wprefix,
-                              const int* total, int64_t* out_off)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s > nsets) return;
-    const int key = gstart[s];
-    int64_t v;
-    if (key >= N) {
-        v = *total;
-    } else {
-        const int w = key >> 6;
-        v = wprefix[w] + __popcll(bitmap[w] & mask_lt(key & 63));
-    }
-    out_off[s] = v;
-}
-
-// int64 set offsets -> int32 group starts, with validation.
-__global__ void k_prep_sets(const int64_t* set_off, int nsets, int64_t n_total, int* gstart, int* err)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s > nsets) return;
-    const int64_t v = set_off[s];
-    bool bad = v < 0 || v > n_total;
-    if (s == 0 && v != 0) bad = true;
-    if (s == nsets && v != n_total) bad = true;
-    if (s > 0 && set_off[s - 1] > v) bad = true;
-    if (bad) atomicOr(err, kErrBounds);
-    gstart[s] = bad ? 0 : (int)v;
-}
-
-__global__ void k_single_set(int* gstart, int n)
-{
-    if (threadIdx.x == 0) { gstart[0] = 0; gstart[1] = n; }
-}
-
 }  // namespace sqh

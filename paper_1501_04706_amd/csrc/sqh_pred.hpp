@@ -14,6 +14,53 @@
 
 namespace sqh {
 
+// Loads and stores through pointers that live in structs lose their address
+// space and compile to FLAT instructions; these casts keep them GLOBAL.
+// Structs move as 16-, 8- or 4-byte words (clang vector types have no user
+// constructors, so they copy across address spaces).
+#define SQH_GLOBAL __attribute__((address_space(1)))
+typedef unsigned int sqh_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int sqh_u32x2 __attribute__((ext_vector_type(2)));
+
+template <class W, class T>
+__device__ __forceinline__ T gld_words(const T* p)
+{
+    constexpr int n = (int)(sizeof(T) / sizeof(W));
+    const SQH_GLOBAL W* q = (const SQH_GLOBAL W*)p;
+    W w[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i] = q[i];
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+template <class W, class T>
+__device__ __forceinline__ void gst_words(T* p, const T& v)
+{
+    constexpr int n = (int)(sizeof(T) / sizeof(W));
+    W w[n];
+    __builtin_memcpy(w, &v, sizeof(T));
+    SQH_GLOBAL W* q = (SQH_GLOBAL W*)p;
+#pragma unroll
+    for (int i = 0; i < n; ++i) q[i] = w[i];
+}
+template <class T>
+__device__ __forceinline__ T gld(const T* p)
+{
+    if constexpr (__is_arithmetic(T)) return *(const SQH_GLOBAL T*)p;
+    else if constexpr (sizeof(T) % 16 == 0) return gld_words<sqh_u32x4>(p);
+    else if constexpr (sizeof(T) % 8 == 0) return gld_words<sqh_u32x2>(p);
+    else return gld_words<unsigned int>(p);
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, const T& v)
+{
+    if constexpr (__is_arithmetic(T)) *(SQH_GLOBAL T*)p = v;
+    else if constexpr (sizeof(T) % 16 == 0) gst_words<sqh_u32x4>(p, v);
+    else if constexpr (sizeof(T) % 8 == 0) gst_words<sqh_u32x2>(p, v);
+    else gst_words<unsigned int>(p, v);
+}
+
 // Orientation of p against the directed edge o -> e:
 //   orient = (ex - ox) * (py - oy) - (ey - oy) * (px - ox)
 // > 0: p left of o->e;  < 0: p right of o->e (outside a counter-clockwise
@@ -145,6 +192,26 @@ __device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float e
     return expansion_sign(t);
 }
 
+// Filter-only sign: +-1 when certified, 0 when undecided (the exact sign may
+// be 0 or not). `fp64_only` leaves every case undecided.
+__device__ __forceinline__ int fast_sign(const Orient32& o, bool fp64_only)
+{
+    const bool ok = !fp64_only && fabsf(o.d) > o.es;
+    return ok ? (o.d > 0.0f ? 1 : -1) : 0;
+}
+
+// Settles undecided signs with the exact path; the exact code runs only if
+// some lane of the wave needs it.
+__device__ __forceinline__ void settle(int& s, bool need, const Edge& E, float px, float py, uint32_t& n_exact)
+{
+    if (__ballot(need)) {
+        if (need) {
+            s = orient_exact(E.ox, E.oy, E.ex, E.ey, px, py);
+            ++n_exact;
+        }
+    }
+}
+
 // Exact sign of orient(o, e, p), filtered. `fp64_only` skips the filter.
 // Also returns the float32 estimate for the farthest-point interval.
 __device__ __forceinline__ int orient_sign(const Edge& E, float px, float py, bool fp64_only,
@@ -160,18 +227,17 @@ __device__ __forceinline__ int orient_sign(const Edge& E, float px, float py, bo
 //
 // A candidate is a point strictly right of its segment's edge. `a` is the
 // float32 estimate of its area -orient (positive), `w` a bound on the
-// estimate's error, `pos` its slot in the pass input (-1: no candidate).
+// estimate's error, `id` its input index (-1: no candidate).
 struct Cand {
     float a, w;
     float x, y;
     int id;
-    int pos;
 };
 
 __device__ __forceinline__ Cand no_cand()
 {
     Cand c;
-    c.a = 0.0f; c.w = 0.0f; c.x = 0.0f; c.y = 0.0f; c.id = 0x7fffffff; c.pos = -1;
+    c.a = 0.0f; c.w = 0.0f; c.x = 0.0f; c.y = 0.0f; c.id = -1;
     return c;
 }
 
@@ -184,8 +250,8 @@ __device__ __forceinline__ Cand no_cand()
 __device__ __forceinline__ bool beats(const Edge& E, const Cand& P, const Cand& Q, bool fp64_only,
                                       uint32_t& n_exact)
 {
-    if (Q.pos < 0) return P.pos >= 0;
-    if (P.pos < 0) return false;
+    if (Q.id < 0) return P.id >= 0;
+    if (P.id < 0) return false;
     if (!fp64_only) {
         // fl(x) > fl(y) implies x > y (rounding is monotone), so these
         // certify area(P) >= P.a - P.w > Q.a + Q.w >= area(Q).
@@ -200,13 +266,26 @@ __device__ __forceinline__ bool beats(const Edge& E, const Cand& P, const Cand& 
     return E.fwd ? p_first : !p_first;
 }
 
+// Farthest-point comparison without the exact path: 1 if P certainly beats
+// Q, 0 if it certainly does not, -1 if undecided.
+__device__ __forceinline__ int beats_fast(const Cand& P, const Cand& Q, bool fp64_only)
+{
+    const bool qn = Q.id < 0, pn = P.id < 0;
+    const bool win = P.a - P.w > Q.a + Q.w;
+    const bool lose = Q.a - Q.w > P.a + P.w;
+    int r = (fp64_only || !(win || lose)) ? -1 : (win ? 1 : 0);
+    r = pn ? 0 : r;
+    r = qn ? (pn ? 0 : 1) : r;
+    return r;
+}
+
 // Candidate for a point known to be strictly right of E (orient < 0).
-__device__ __forceinline__ Cand make_cand(const Orient32& o, float x, float y, int id, int pos)
+__device__ __forceinline__ Cand make_cand(const Orient32& o, float x, float y, int id)
 {
     Cand c;
     c.a = -o.d;
     c.w = 2.0f * o.es;
-    c.x = x; c.y = y; c.id = id; c.pos = pos;
+    c.x = x; c.y = y; c.id = id;
     return c;
 }
 

@@ -15,7 +15,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsqh.so")
+# SQH_LIB may name another build of the same library (A/B measurements)
+LIB_PATH = os.environ.get("SQH_LIB") or os.path.join(HERE, "libsqh.so")
 
 SQH_OK = 0
 SQH_EINVAL = -1
@@ -41,10 +42,14 @@ class SqhError(RuntimeError):
         super().__init__(msg)
 
 
+SQH_MAX_TIMED_PASSES = 64
+
+
 class SqhStats(ctypes.Structure):
     _fields_ = [
         ("passes", ctypes.c_int64),
         ("points", ctypes.c_int64),
+        ("first_survivors", ctypes.c_int64),
         ("survivors_total", ctypes.c_int64),
         ("orient_evals", ctypes.c_int64),
         ("orient_exact", ctypes.c_int64),
@@ -52,10 +57,25 @@ class SqhStats(ctypes.Structure):
         ("hull_size", ctypes.c_int64),
         ("max_segments", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
+        ("ms_seed", ctypes.c_double),
+        ("ms_split", ctypes.c_double),
+        ("ms_first", ctypes.c_double),
+        ("ms_pass", ctypes.c_double),
+        ("ms_table", ctypes.c_double),
+        ("ms_emit", ctypes.c_double),
+        ("pass_points", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
+        ("pass_segments", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
+        ("pass_ms", ctypes.c_double * SQH_MAX_TIMED_PASSES),
     ]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            if k.startswith("pass_"):
+                v = list(v)[: min(self.passes, SQH_MAX_TIMED_PASSES)]
+            d[k] = v
+        return d
 
 
 def load() -> ctypes.CDLL:
@@ -82,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.sqh_hull_batched.restype = c_int
     lib.sqh_get_stats.argtypes = [vp, ctypes.POINTER(SqhStats)]
     lib.sqh_get_stats.restype = c_int
+    lib.sqh_get_trace.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), c_int]
+    lib.sqh_get_trace.restype = c_int
     lib.sqh_strerror.argtypes = [c_int]
     lib.sqh_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -143,6 +165,14 @@ def sqh_get_stats(ctx: int) -> dict:
     if rc != SQH_OK:
         raise SqhError(rc, "sqh_get_stats")
     return st.as_dict()
+
+
+def sqh_get_trace(ctx: int, max_entries: int = 8 * 512) -> list:
+    buf = (ctypes.c_uint64 * max_entries)()
+    n = load().sqh_get_trace(ctx, buf, max_entries)
+    if n < 0:
+        raise SqhError(n, "sqh_get_trace")
+    return list(buf[:n])
 
 
 def sqh_strerror(code: int) -> str:

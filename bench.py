@@ -31,30 +31,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL = "k_hull"      # the persistent kernel that runs the whole hull
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_bytes(st: dict, n: int) -> dict:
-    """Algorithmic HBM bytes per kernel kind for one hull call.
+def kernel_bytes(st: dict, n: int) -> int:
+    """Algorithmic HBM bytes of one hull-kernel launch (one sqh_hull call).
 
     seed   reads the (x, y) input once: 8 B/pt
     split  reads it again: 8 B/pt
     first  reads it a third time and writes each survivor (x, y, index): 12 B
     pass   reads each point entering the pass (12 B) and writes each point
            kept for the next pass (12 B)
+    Segment tables, counters and the output are O(h + segments) and left out.
     """
-    pts = list(st["pass_points"])
-    passes = len(pts)
+    pts = list(st["pass_points"])[: int(st["passes"])]
     pass_bytes = 0
-    for k in range(passes):
-        nxt = pts[k + 1] if k + 1 < passes else 0
-        pass_bytes += 12 * pts[k] + 12 * nxt
-    return {
-        "seed": (8 * n, 1),
-        "split": (8 * n, 1),
-        "first": (8 * n + 12 * st["first_survivors"], 1),
-        "pass": (pass_bytes, max(passes, 1)),
-    }
+    for k, v in enumerate(pts):
+        nxt = pts[k + 1] if k + 1 < len(pts) else 0
+        pass_bytes += 12 * v + 12 * nxt
+    return 8 * n + 8 * n + 8 * n + 12 * int(st["first_survivors"]) + pass_bytes
 
 
 def load_traffic(kernel: str):
@@ -104,6 +100,168 @@ def cpu_baseline(xy, budget_s: float = 25.0) -> dict:
     }
 
 
+def bench_batched(H, sqh, torch, workloads, total, steps: int, warmup: int, seed: int = 4) -> dict:
+    """4096 independent sets (log-uniform sizes in [64, 2^20], kinds drawn from
+    square/disk/circle) as one batched call, against one sqh_hull call per set
+    on the same GPU, the same build and the same device-resident sets."""
+    import numpy as np
+    b = workloads.batch(4096, seed=seed, total=total)
+    dev = torch.device("cuda", 0)
+    xy_d = torch.from_numpy(b.xy).to(dev)
+    off_d = torch.from_numpy(b.offsets).to(dev)
+    n_total = int(b.offsets[-1])
+    out = torch.empty(max(n_total, 1), dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        H.hull_batched(xy_d, off_d, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = 0.0
+    for _ in range(steps):
+        hv, _ = H.hull_batched(xy_d, off_d, out=out)
+        kern += H.stats()["ms_kernel"]
+    torch.cuda.synchronize()
+    ms_batched = (time.perf_counter() - t0) * 1000.0 / steps
+    st = H.stats()
+
+    # one hull per launch: each set through sqh_hull, synchronising per hull
+    sizes = np.diff(b.offsets)
+    H.workspace(int(sizes.max()), 1)
+    out1 = torch.empty(int(sizes.max()), dtype=torch.int32, device=dev)
+    views = [xy_d[int(b.offsets[s]):int(b.offsets[s + 1])] for s in range(b.nsets)]
+    for v in views[:64]:
+        H.hull(v, out=out1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        H.hull(v, out=out1)
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t0) * 1000.0
+    hps_b = b.nsets / (ms_batched / 1000.0)
+    hps_l = b.nsets / (ms_loop / 1000.0)
+    del xy_d, off_d, out, out1
+    return {
+        "workload": f"4096 sets, log-uniform sizes in [64, 2^20]"
+                    + (f" rescaled to about {total} points" if total else "")
+                    + f", square/disk/circle, seed {seed}",
+        "points": n_total,
+        "hulls_per_s": round(hps_b, 1),
+        "ms_per_batch": round(ms_batched, 3),
+        "kernel_ms_per_batch": round(kern / steps, 3),
+        "Mpoints_per_s": round(n_total / (ms_batched / 1000.0) / 1e6, 1),
+        "hull_vertices": int(hv.numel()),
+        "passes": int(st["passes"]),
+        "per_hull_loop_hulls_per_s": round(hps_l, 1),
+        "per_hull_loop_ms": round(ms_loop, 2),
+        "speedup_vs_per_hull_loop": round(hps_b / hps_l, 2),
+    }
+
+
+def _percentiles(lat_ms):
+    import numpy as np
+    v = np.asarray(lat_ms, dtype=np.float64)
+    return {"p50_ms": round(float(np.percentile(v, 50)), 3), "p99_ms": round(float(np.percentile(v, 99)), 3),
+            "mean_ms": round(float(v.mean()), 3)}
+
+
+def bench_serving(H, sqh, torch, workloads, count: int = 600, pool: int = 48, max_passes: int = 8,
+                  seed: int = 5) -> dict:
+    """Poisson stream of hull requests (sizes log-uniform in [1e3, 4e6], kinds
+    square/disk/circle) from host memory. The engine (continuous batching)
+    against one sqh_hull per request in arrival order (the plain path), both
+    timed from arrival to the hull indices in host memory."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = workloads.log_uniform_sizes(rng, pool, 1000, 4_000_000)
+    kinds = ("square", "disk", "circle")
+    which = rng.integers(0, 3, size=pool)
+    child = np.random.SeedSequence(seed).spawn(pool)
+    sets = [workloads.make(kinds[which[i]], int(sizes[i]), int(child[i].generate_state(1)[0]))
+            for i in range(pool)]
+    pick = rng.integers(0, pool, size=count)
+    dev = torch.device("cuda", 0)
+
+    def run_engine(H_, arrivals):
+        E = H_.engine(1 << 25, 1024, 1 << 24)
+        try:
+            res = {}
+            done_t = {}
+            t0 = time.perf_counter()
+            nxt = 0
+            while len(done_t) < count:
+                now = time.perf_counter() - t0
+                while nxt < count and arrivals[nxt] <= now and E.admit(sets[pick[nxt]], nxt):
+                    nxt += 1
+                st = E.status()
+                if st["resident"] + st["staged"] == 0:
+                    if nxt < count:
+                        time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+                    continue
+                E.step(max_passes)
+                while True:
+                    r = E.poll()
+                    if r is None:
+                        break
+                    done_t[r[0]] = time.perf_counter() - t0
+                    res[r[0]] = r[1]
+            wall = max(done_t.values())
+            lat = [(done_t[i] - arrivals[i]) * 1000.0 for i in range(count)]
+            return wall, lat, res
+        finally:
+            E.close()
+
+    def run_plain(arrivals):
+        out = torch.empty(4_000_000, dtype=torch.int32, device=dev)
+        H.workspace(4_000_000, 1)
+        t0 = time.perf_counter()
+        lat = []
+        res = {}
+        for i in range(count):
+            now = time.perf_counter() - t0
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            xy = torch.from_numpy(sets[pick[i]]).to(dev)
+            hv = H.hull(xy, out=out).cpu().numpy()
+            t = time.perf_counter() - t0
+            lat.append((t - arrivals[i]) * 1000.0)
+            res[i] = hv
+        return time.perf_counter() - t0, lat, res
+
+    zero = np.zeros(count)
+    run_engine(H, zero)  # warm-up
+    wall_e, _, res_e = run_engine(H, zero)
+    T = count / wall_e
+    wall_p, _, res_p = run_plain(zero)
+    Tp = count / wall_p
+    same = all(np.array_equal(res_e[i], res_p[i]) for i in range(count))
+    H64 = sqh.Hull(0, precision=sqh.SQH_FP64_ONLY)
+    try:
+        wall_64, _, res_64 = run_engine(H64, zero)
+    finally:
+        H64.close()
+    same64 = all(np.array_equal(res_e[i], res_64[i]) for i in range(count))
+    out = {
+        "workload": f"{count} requests drawn from {pool} point sets, sizes log-uniform in [1e3, 4e6], "
+                    f"square/disk/circle, seed {seed}, host input, {max_passes} passes per engine step",
+        "saturated_hulls_per_s": round(T, 1),
+        "plain_saturated_hulls_per_s": round(Tp, 1),
+        "speedup_vs_plain": round(T / Tp, 2),
+        "fp64_only_saturated_hulls_per_s": round(count / wall_64, 1),
+        "fp32_filter_vs_fp64_only": round(T / (count / wall_64), 3),
+        "identical_to_plain": bool(same),
+        "fp64_identical": bool(same64),
+    }
+    for frac in (0.5, 0.8):
+        lam = frac * T
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / lam, size=count)
+        arr = np.cumsum(gaps)
+        _, lat_e, _ = run_engine(H, arr)
+        _, lat_p, _ = run_plain(arr)
+        out[f"qps_{frac}T"] = round(lam, 1)
+        out[f"engine_{frac}T"] = _percentiles(lat_e)
+        out[f"plain_{frac}T"] = _percentiles(lat_p)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +270,16 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=20_000_000)
     ap.add_argument("--kind", default="square", choices=["square", "disk", "circle", "grid"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
+                    help="fp32: float32 filter with exact fallback; fp64: every predicate exact")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=600, help="serving requests (0: skip)")
+    ap.add_argument("--batch", default="64M", choices=["64M", "full", "none"],
+                    help="batched comparison: 4096 sets rescaled to ~64M points, the literal "
+                         "log-uniform sizes (~4.4e8 points), or skip it")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device-to-device copy of the 20M-point input "
+                         "(160 MB read + 160 MB written per launch), to scale HBM counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -125,17 +292,29 @@ def main() -> int:
     import torch
     from paper_1501_04706_amd import sqh, workloads
 
-    xy = workloads.make(args.kind, args.n, args.seed)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.empty((args.n, 2), dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return 0
+    xy = workloads.make(args.kind, args.n, args.seed)
     xy_d = torch.from_numpy(xy).to(dev)
     H = sqh.Hull(0)
+    if args.precision == "fp64":
+        H.set_precision(sqh.SQH_FP64_ONLY)
     out = torch.empty(max(args.n, 1), dtype=torch.int32, device=dev)
     H.workspace(args.n, 1)
     for _ in range(args.warmup):
         H.hull(xy_d, out=out)
     torch.cuda.synchronize()
 
-    agg = {k: 0.0 for k in ("ms_seed", "ms_split", "ms_first", "ms_pass", "ms_table", "ms_emit", "ms_total")}
+    keys = ("ms_total", "ms_kernel", "ms_seed", "ms_split", "ms_first", "ms_pass", "ms_emit")
+    agg = {k: 0.0 for k in keys}
     exact = evals = cmpx = 0
     last = None
     t0 = time.perf_counter()
@@ -153,16 +332,10 @@ def main() -> int:
     ms_step = (t1 - t0) * 1000.0 / args.steps
     value = args.n / (ms_step / 1000.0) / 1e6
 
-    kb = kernel_bytes(last, args.n)
-    per_kind_ms = {"seed": agg["ms_seed"], "split": agg["ms_split"], "first": agg["ms_first"],
-                   "pass": agg["ms_pass"]}
-    dom = max(per_kind_ms, key=lambda k: per_kind_ms[k])
-    nbytes, launches = kb[dom]
-    avg_launch_ms = per_kind_ms[dom] / args.steps / launches
-    achieved = (nbytes / launches) / (avg_launch_ms / 1000.0) / 1e9
-    names = {"seed": "k_tiles<PolSeed>", "split": "k_tiles<PolSplit>", "first": "k_tiles<PolFirst>",
-             "pass": "k_tiles<PolPass>"}
-    traffic = load_traffic(names[dom])
+    nbytes = kernel_bytes(last, args.n)
+    avg_launch_ms = agg["ms_kernel"] / args.steps
+    achieved = nbytes / (avg_launch_ms / 1000.0) / 1e9
+    traffic = load_traffic(KERNEL)
 
     line = {
         "metric": "Mpoints/s + HBM GB/s (20M-pt hull); batched hulls/s & p99 latency vs plain",
@@ -178,29 +351,36 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"single hull, {args.kind}, n={args.n}, float32, seed {args.seed}",
-                   "n": args.n, "kind": args.kind, "seed": args.seed},
+                   "n": args.n, "kind": args.kind, "seed": args.seed,
+                   "precision": args.precision},
         "roofline": {
             "bound": "hbm",
-            "kernel": names[dom],
+            "kernel": KERNEL,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "alg_bytes_per_launch": int(nbytes / launches),
+            "alg_bytes_per_launch": int(nbytes),
             "avg_launch_ms": round(avg_launch_ms, 5),
         },
         "detail": {
             "hull_size": int(last["hull_size"]),
             "passes": int(last["passes"]),
-            "kernel_ms_per_step": {k[3:]: round(v / args.steps, 4) for k, v in agg.items()},
-            "alg_bytes_per_step": int(sum(b for b, _ in kb.values())),
-            "alg_GBps_whole_call": round(sum(b for b, _ in kb.values()) / (ms_step / 1000) / 1e9, 1),
+            "ms_per_call": {k[3:]: round(v / args.steps, 4) for k, v in agg.items()},
+            "one_read_floor_frac": round(8 * args.n / (ms_step / 1000) / 1e9 / HBM_PEAK_GBS, 4),
             "orient_fallback_rate": (exact / evals) if evals else 0.0,
-            "cmp_exact_per_step": cmpx / args.steps,
-            "pass_points": list(last["pass_points"]),
+            "orient_evals_per_call": evals / args.steps,
+            "cmp_exact_per_call": cmpx / args.steps,
+            "pass_points": list(last["pass_points"])[: int(last["passes"])],
         },
     }
+    if args.batch != "none":
+        line["batched"] = bench_batched(H, sqh, torch, workloads,
+                                        64_000_000 if args.batch == "64M" else None,
+                                        steps=3, warmup=1)
+    if args.serve > 0:
+        line["serving"] = bench_serving(H, sqh, torch, workloads, count=args.serve)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(xy)
     else:

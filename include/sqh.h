@@ -62,9 +62,11 @@ typedef struct sqh_ctx sqh_ctx;
 
 #define SQH_MAX_TIMED_PASSES 64
 
-/* Per-call counters of the last sqh_hull / sqh_hull_batched call. Kernel
- * times come from HIP events recorded on the call's stream around each
- * launch. */
+/* Per-call counters of the last sqh_hull / sqh_hull_batched call.
+ * ms_total and ms_kernel come from HIP events recorded on the call's stream;
+ * the phase times are differences of the device's constant 100 MHz clock read
+ * by workgroup 0 at the end of each phase of the persistent kernel (each
+ * phase ends at a grid-wide barrier, so they partition ms_kernel). */
 typedef struct sqh_stats {
     int64_t passes;           /* segmented passes after the first compaction */
     int64_t points;           /* input points */
@@ -75,8 +77,9 @@ typedef struct sqh_stats {
     int64_t cmp_exact;        /* farthest-point comparisons decided exactly */
     int64_t hull_size;        /* total hull vertices (all sets) */
     int64_t max_segments;     /* largest number of active segments in a pass */
-    double  ms_total;         /* device time of the whole call */
-    double  ms_seed, ms_split, ms_first, ms_pass, ms_table, ms_emit;  /* kernel times */
+    double  ms_total;         /* device time of the whole call: workspace reset + hull kernel */
+    double  ms_kernel;        /* the persistent hull kernel alone */
+    double  ms_seed, ms_split, ms_first, ms_pass, ms_emit;  /* phases of the hull kernel */
     int64_t pass_points[SQH_MAX_TIMED_PASSES];    /* points entering pass k */
     int64_t pass_segments[SQH_MAX_TIMED_PASSES];  /* segments in pass k */
     double  pass_ms[SQH_MAX_TIMED_PASSES];        /* kernel time of pass k */
@@ -143,6 +146,146 @@ int sqh_hull(sqh_ctx *ctx, const float *d_xy, int64_t n, int32_t *d_out, int64_t
 int sqh_hull_batched(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, int64_t n_sets,
                      int64_t n_total, int32_t *d_out, int64_t *d_out_off, int64_t out_cap,
                      int64_t *h_total, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Launch-shape autotuner (not part of the paper's method; it chooses how the
+ * same computation is laid out on the device). Runs the batched problem
+ * described by the arguments (as sqh_hull_batched; d_set_off and d_out_off
+ * may be NULL when n_sets == 1) once per candidate shape plus `reps` timed
+ * repetitions (1..100), and stores the fastest shape in the context for
+ * this problem's size class, floor(log2(n_total)). Candidates: the number of
+ * workgroups of the persistent kernel (all co-resident ones, 3/4, 1/2, 1/4)
+ * times the tail threshold (2^14, 2^16, 2^18 points) below which one
+ * workgroup finishes the remaining passes. Later calls of any size use the
+ * entry of the nearest class. The output of every shape is identical; only
+ * time differs. Leaves the last candidate's result in d_out. Returns as
+ * sqh_hull_batched, or SQH_ENOMEM when the context's table (40 classes) is
+ * full. Synchronises the stream.
+ */
+int sqh_autotune(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, int64_t n_sets, int64_t n_total,
+                 int32_t *d_out, int64_t *d_out_off, int64_t out_cap, void *d_ws, size_t ws_bytes,
+                 void *stream, int reps);
+
+/*
+ * The context's tuning table as JSON,
+ *   {"entries": [{"log2n": K, "grid": G, "tail": T}, ...]}
+ * written NUL-terminated into host buffer `buf` of `len` bytes (truncated
+ * if short; buf may be NULL). Returns the length the full text needs,
+ * including the NUL, or SQH_EINVAL.
+ */
+int sqh_get_tuning(const sqh_ctx *ctx, char *buf, size_t len);
+
+/*
+ * Replace the context's tuning table with the entries of `json` (the format
+ * of sqh_get_tuning; an empty list restores the built-in shape). Rejects the
+ * whole text with SQH_EINVAL if an entry lacks a key or has grid outside
+ * [1, co-resident workgroups of this device] or a negative tail.
+ */
+int sqh_set_tuning(sqh_ctx *ctx, const char *json);
+
+/*
+ * A HIP graph of one batched hull on fixed buffers: a kernel node that
+ * resets the workspace and the persistent kernel's node (launched as a
+ * cooperative kernel), with the launch shape chosen by the context's tuning
+ * table when the graph is created. The arguments are those of
+ * sqh_hull_batched (d_set_off and d_out_off may be NULL when n_sets == 1);
+ * the buffers must outlive the graph, and their contents (points, set
+ * offsets) are read at every launch, so the caller may refill them between
+ * launches with the same sizes. The graph captures the precision mode at
+ * creation. Returns SQH_OK and *graph, or the codes of sqh_hull_batched.
+ */
+typedef struct sqh_graph sqh_graph;
+int sqh_graph_create(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, int64_t n_sets,
+                     int64_t n_total, int32_t *d_out, int64_t *d_out_off, int64_t out_cap, void *d_ws,
+                     size_t ws_bytes, sqh_graph **graph);
+
+/* Enqueue one replay of the graph on `stream`. Does not synchronise;
+ * d_out / d_out_off are valid once the stream reaches this point. Launches
+ * of one graph (or of anything sharing its workspace) must not overlap. */
+int sqh_graph_launch(sqh_graph *graph, void *stream);
+
+/* Synchronise `stream`, then read the status of the graph's last replay:
+ * *h_total (host, may be NULL) receives the total hull vertices, and the
+ * context's counters (sqh_get_stats) are filled, except the event times.
+ * Returns as sqh_hull_batched. */
+int sqh_graph_result(sqh_graph *graph, int64_t *h_total, void *stream);
+
+/* Destroy a graph. NULL is ignored. */
+void sqh_graph_destroy(sqh_graph *graph);
+
+/*
+ * Serving engine: continuous batching of hull requests over one device
+ * arena (an extension beyond the paper: the paper's segments -- section 2,
+ * Table 1 -- of many independent requests share one segment table).
+ *
+ * The arena is caller-owned device memory of sqh_engine_bytes(slots,
+ * max_requests, stage_points) bytes. A request of n points occupies n slots
+ * (rounded up to 64) from admission until its hull has been collected:
+ * admission is by this footprint. Admitted points wait in a staging area of
+ * stage_points points until the next step. Every step
+ *   - runs the seed, first split and first compaction (sections 4.3-4.4) of
+ *     the requests admitted since the last step and appends their segments to
+ *     the resident segment table,
+ *   - runs up to max_passes passes (section 4.4) over the segments of every
+ *     resident request at once, so new and old requests share each launch,
+ *   - emits the hulls of the requests left without segments (same result
+ *     convention as sqh_hull, indices local to the request) and frees their
+ *     slots.
+ * An engine is used by one host thread; its calls are stream-ordered on the
+ * stream passed, and sqh_engine_step synchronises that stream.
+ */
+typedef struct sqh_engine sqh_engine;
+
+/* Arena bytes for `slots` (a multiple of 64, 64 <= slots <= 2^31 - 128)
+ * point slots, up to max_requests (1 .. 2^20) requests in flight and a
+ * staging area of stage_points (1 .. slots) points. 0 if out of range. */
+size_t sqh_engine_bytes(int64_t slots, int64_t max_requests, int64_t stage_points);
+
+/* Create an engine over device arena d_arena of arena_bytes bytes
+ * (>= sqh_engine_bytes). The context supplies the device, the precision
+ * mode and the launch-shape tuning; it must outlive the engine. Returns
+ * SQH_OK, SQH_EINVAL, SQH_ENOMEM (arena too small) or SQH_EDEVICE. */
+int sqh_engine_create(sqh_ctx *ctx, void *d_arena, size_t arena_bytes, int64_t slots, int64_t max_requests,
+                      int64_t stage_points, sqh_engine **engine);
+
+/* Destroy an engine (the arena stays the caller's). NULL is ignored. */
+void sqh_engine_destroy(sqh_engine *engine);
+
+/*
+ * Admit one request of n (x, y) float32 points, copied from `xy` (host
+ * memory if on_device == 0, else device memory) into the staging area on
+ * `stream`; `tag` identifies it in sqh_engine_poll. Returns SQH_OK;
+ * SQH_EBUSY when its slots, the staging area or the request table have no
+ * room now (retry after a step); SQH_EINVAL for a null pointer, n < 0 or n
+ * larger than the slots or the staging area; SQH_EDEVICE. n == 0 finishes
+ * at once with an empty hull. Non-finite coordinates are reported by
+ * sqh_engine_poll for that request only.
+ */
+int sqh_engine_admit(sqh_engine *engine, const float *xy, int64_t n, uint64_t tag, int on_device,
+                     void *stream);
+
+/*
+ * One step (see above) with at most max_passes (1 .. 65536) passes.
+ * Returns the number of requests that finished in this step (their hulls
+ * are then waiting for sqh_engine_poll), or SQH_EINVAL / SQH_EDEVICE (the
+ * engine is unusable after SQH_EDEVICE). Synchronises the stream.
+ */
+int sqh_engine_step(sqh_engine *engine, int max_passes, void *stream);
+
+/*
+ * Take the oldest finished request: *tag receives its tag and *h its hull
+ * size; up to cap indices go to host array h_out. Returns SQH_OK;
+ * SQH_ENOTFOUND if none is finished; SQH_ECAPACITY if h > cap (the result
+ * stays queued: call again with a larger buffer); SQH_EINVAL if the
+ * request had a non-finite coordinate (the request is consumed, h = 0).
+ */
+int sqh_engine_poll(sqh_engine *engine, uint64_t *tag, int32_t *h_out, int64_t cap, int64_t *h);
+
+/* Counts of resident (in the segment table), staged (admitted, not yet
+ * stepped) and finished-but-not-polled requests, and free slots; any
+ * pointer may be NULL. Returns SQH_OK, or SQH_EDEVICE after a failed step. */
+int sqh_engine_status(const sqh_engine *engine, int64_t *resident, int64_t *staged, int64_t *finished,
+                      int64_t *free_slots);
 
 /* Counters of the last hull call on this context. */
 int sqh_get_stats(const sqh_ctx *ctx, sqh_stats *out);

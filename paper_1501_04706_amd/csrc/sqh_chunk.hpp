@@ -236,6 +236,81 @@ __device__ __forceinline__ void row_one_group(const Pol& pol, const typename Pol
     }
 }
 
+// Groups g, g+1, ... that start at or after qs and end at or before re,
+// inside the row [q, re) of one wave (qs > q, and g ends before re): every
+// lane takes its own group's context; ranks come from the ballot of its
+// bucket masked to its group's lanes, and the farthest point of each group
+// and bucket from a segmented inclusive shuffle scan, whose last lane
+// finalises the group. Needs non-empty groups (at most 63 then start inside
+// a row, so the starts of g .. g+63 give every end). On return qs is the end
+// of the last such group and g, ge, c describe the group holding it, or
+// open is false if the wave's part ends there.
+template <class Pol, int MODE>
+__device__ __forceinline__ void middle_groups(const Pol& pol, int q, int& qs, int re, int we, int& g, int& ge,
+                                              typename Pol::Ctx& c, bool& open, Counters& ctr)
+{
+    constexpr int NB = Pol::NB;
+    using Ctx = typename Pol::Ctx;
+    const int lane = lane_id();
+    const int G = pol.num_groups();
+    // starts of groups g + lane; group_start(G) is the end of the last group
+    const int stl = (g + lane <= G) ? pol.group_start(g + lane) : 0x7fffffff;
+    const int m = __popcll(__ballot(lane >= 1 && stl <= re));  // groups ending at or before re
+    const int emid = rl_i(stl, m);
+    const int pos = q + lane;
+    const bool in_mid = pos >= qs && pos < emid;
+    // this lane's group: the largest j < m with start(g + j) <= pos
+    int j = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int t = j + step;
+        const int st = __shfl(stl, t & 63);
+        if (t < m && st <= pos) j = t;
+    }
+    const int gs_l = __shfl(stl, j), ge_l = __shfl(stl, j + 1);
+    const int gl = g + j;
+    const Ctx cl = pol.ctx(gl);
+    float x = 0.0f, y = 0.0f;
+    int id = 0;
+    Cand cand;
+    int bk = kNone;
+    if (in_mid) {
+        pol.load(cl, gl, pos, x, y, id);
+        bk = pol.classify(cl, gl, pos, x, y, id, cand, ctr);
+    }
+    const int lo = gs_l - q;  // first lane of this lane's group
+    const uint64_t gm = mask_range(lo, ge_l - q - 1);
+    Agg<NB> tot;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const uint64_t M = __ballot(bk == k);
+        tot.cnt[k] = __popcll(M & gm);
+        if constexpr (MODE == kModeScatter && Pol::SCATTER) {
+            if (bk == k) pol.store(pol.place(cl, gl, k, __popcll(M & gm & mask_lt(lane))), x, y, id);
+        }
+        if constexpr (MODE == kModeAgg) {
+            Cand v = bk == k ? cand : no_cand();
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const Cand o = shfl_up_cand(v, d);
+                if (lane - d >= lo && pol.beats(cl, k, o, v, ctr)) v = o;
+            }
+            tot.best[k] = v;
+        }
+    }
+    if constexpr (MODE == kModeAgg) {
+        if (in_mid && pos == ge_l - 1) pol.finalize(cl, gl, tot);
+    }
+    qs = emid;
+    g += m;
+    if (emid >= we) {
+        open = false;
+    } else {
+        ge = pol.group_end(g);
+        c = pol.ctx(g);
+    }
+}
+
 // One wave streams [wb, we), a part of chunk [cb, ..) whose groups are
 // glo..ghi. kModeAgg: finalises groups that start and end inside the part,
 // records the part's first group if it started before wb and ends inside
@@ -337,6 +412,10 @@ __device__ __forceinline__ void process_wave(const Pol& pol, int wb, int we, int
             qs = ge;
             end_group();
             if (!open || qs >= re) break;
+            if constexpr (Pol::MIDDLE) {
+                if (ge < re) middle_groups<Pol, MODE>(pol, q, qs, re, we, g, ge, c, open, ctr);
+                if (!open || qs >= re) break;
+            }
         }
         q = re;
     }

@@ -6,10 +6,16 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
 #include <new>
+#include <vector>
+#include <deque>
 
 #include "../../include/sqh.h"
 #include "sqh_kernels.hip"
+#include "sqh_engine.hip"
 
 using namespace sqh;
 
@@ -75,17 +81,34 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
 
 }  // namespace
 
+struct TuneEntry {
+    int log2n;  // problem class: floor(log2(max(n_total, 1)))
+    int grid;   // workgroups of the persistent kernel
+    int tail;   // tail threshold (points) below which workgroup 0 finishes alone
+};
+
 struct sqh_ctx {
     int device = 0;
     int cus = 0;
     int fp64 = 0;
-    int grid = 0;  // co-resident workgroups of k_hull
-    int trace = 0; // SQH_TRACE=1: per-workgroup timestamps in the info block
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    HullInfo* hinfo = nullptr;  // pinned host copy of the info block
+    int max_grid = 0;  // co-resident workgroups of k_hull
+    int trace = 0;     // SQH_TRACE=1: per-workgroup timestamps in the info block
+    hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
+    HullInfo* hinfo = nullptr;   // pinned host copy of the info block
     uint32_t* hstats = nullptr;  // pinned host copy of the counters
     int* herr = nullptr;
     sqh_stats stats{};
+    static constexpr int kMaxTune = 40;
+    TuneEntry tune[kMaxTune];
+    int ntune = 0;
+};
+
+struct sqh_graph {
+    sqh_ctx* ctx = nullptr;
+    HullArgs args{};
+    int64_t N = 0, out_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -95,8 +118,36 @@ namespace {
         if ((expr) != hipSuccess) return SQH_EDEVICE;      \
     } while (0)
 
-int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t* d_set_off, int32_t* d_out,
-        int64_t* d_out_off, int64_t out_cap, int64_t* h_total, void* d_ws, size_t ws_bytes, hipStream_t st)
+int log2_class(int64_t n)
+{
+    int k = 0;
+    while (k < 62 && (int64_t(1) << (k + 1)) <= std::max<int64_t>(n, 1)) ++k;
+    return k;
+}
+
+// Launch shape for a problem of n_total points: the tuned entry of the
+// nearest problem class, else all co-resident workgroups and the built-in
+// tail threshold.
+TuneEntry pick_tuning(const sqh_ctx* ctx, int64_t n_total)
+{
+    TuneEntry t{log2_class(n_total), ctx->max_grid, kTailPoints};
+    int best = 1 << 30;
+    for (int i = 0; i < ctx->ntune; ++i) {
+        const int d = std::abs(ctx->tune[i].log2n - t.log2n);
+        if (d < best) {
+            best = d;
+            t.grid = ctx->tune[i].grid;
+            t.tail = ctx->tune[i].tail;
+        }
+    }
+    t.grid = std::max(1, std::min(t.grid, ctx->max_grid));
+    return t;
+}
+
+// Validate the call and fill the kernel arguments over the caller's workspace.
+int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t* d_set_off, int32_t* d_out,
+          int64_t* d_out_off, int64_t out_cap, void* d_ws, size_t ws_bytes, const TuneEntry& tu, HullArgs& a,
+          int& reset_grid)
 {
     Layout L;
     if (!make_layout(N, nsets, L)) return SQH_EINVAL;
@@ -104,11 +155,12 @@ int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t
     if (out_cap < 0) return SQH_EINVAL;
     if (N > 0 && !d_xy) return SQH_EINVAL;
     if (out_cap > 0 && !d_out) return SQH_EINVAL;
+    if (tu.grid < 1 || tu.grid > ctx->max_grid || tu.grid > kMaxGrid || tu.tail < 0) return SQH_EINVAL;
     HIP_OK(hipSetDevice(ctx->device));
 
     char* ws = static_cast<char*>(d_ws);
     auto at = [&](size_t off) { return static_cast<void*>(ws + off); };
-    HullArgs a;
+    a = HullArgs{};
     a.xy = reinterpret_cast<const float2*>(d_xy);
     a.N = (int)N;
     a.G = (int)nsets;
@@ -143,18 +195,30 @@ int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t
     a.info = static_cast<HullInfo*>(at(L.info));
     a.fp64 = ctx->fp64;
     a.timing = ctx->trace ? 2 : 1;
+    a.tail_points = tu.tail;
+    const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
+    reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
+    return SQH_OK;
+}
 
+// Enqueue the workspace reset and the persistent kernel, bracketed by events.
+int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
+{
     HIP_OK(hipEventRecord(ctx->ev0, st));
-    {
-        const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
-        const int grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
-        k_reset<<<grid, 256, 0, st>>>(a);
-        HIP_OK(hipGetLastError());
-    }
+    k_reset<<<reset_grid, 256, 0, st>>>(a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
-    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull), dim3(ctx->grid), dim3(kBlock), argv,
-                                      0, st));
+    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull), dim3(grid), dim3(kBlock), argv, 0, st));
     HIP_OK(hipEventRecord(ctx->ev1, st));
+    return SQH_OK;
+}
+
+// Read the status words back (synchronising the stream), fill the context's
+// counters and map the device status to a return code.
+int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t* h_total, hipStream_t st,
+            bool timed)
+{
     HIP_OK(hipMemcpyAsync(ctx->hinfo, a.info, ctx->trace ? sizeof(HullInfo) : offsetof(HullInfo, trace),
                           hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(ctx->hstats, a.stats, sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
@@ -181,7 +245,7 @@ int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t
         S.orient_exact += ctx->hstats[4 * i + 1];
         S.cmp_exact += ctx->hstats[4 * i + 2];
     }
-    // device timestamps (100 MHz constant clock) at phase ends, block 0
+    // device timestamps (100 MHz constant clock) at phase ends, workgroup 0
     if (hi.nstamps > 1) {
         const double tick_ms = 1e-5;
         auto dt = [&](int i) { return (double)(hi.stamp[i] - hi.stamp[i - 1]) * tick_ms; };
@@ -199,12 +263,184 @@ int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t
     }
     const int64_t h = hi.h_total;
     S.hull_size = h;
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
+    if (timed) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
+        if (hipEventElapsedTime(&ms, ctx->evk, ctx->ev1) == hipSuccess) S.ms_kernel = ms;
+    }
     if (h_total) *h_total = h;
     if (e & (kErrNonFinite | kErrBounds)) return SQH_EINVAL;
     if (e) return SQH_EDEVICE;
     return h > out_cap ? SQH_ECAPACITY : SQH_OK;
+}
+
+int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t* d_set_off, int32_t* d_out,
+              int64_t* d_out_off, int64_t out_cap, int64_t* h_total, void* d_ws, size_t ws_bytes, hipStream_t st,
+              const TuneEntry& tu)
+{
+    HullArgs a;
+    int reset_grid = 1;
+    int rc = setup(ctx, d_xy, N, nsets, d_set_off, d_out, d_out_off, out_cap, d_ws, ws_bytes, tu, a, reset_grid);
+    if (rc != SQH_OK) return rc;
+    rc = enqueue(ctx, a, reset_grid, tu.grid, st);
+    if (rc != SQH_OK) return rc;
+    return collect(ctx, a, N, out_cap, h_total, st, true);
+}
+
+int run(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t* d_set_off, int32_t* d_out,
+        int64_t* d_out_off, int64_t out_cap, int64_t* h_total, void* d_ws, size_t ws_bytes, hipStream_t st)
+{
+    return run_tuned(ctx, d_xy, N, nsets, d_set_off, d_out, d_out_off, out_cap, h_total, d_ws, ws_bytes, st,
+                     pick_tuning(ctx, N));
+}
+
+// Minimal reader for the tuning format written by sqh_get_tuning:
+//   {"entries": [{"log2n": K, "grid": G, "tail": T}, ...]}
+// Keys may appear in any order inside an entry; unknown keys are ignored.
+bool read_int_key(const char* obj, const char* end, const char* key, long& v)
+{
+    char pat[32];
+    snprintf(pat, sizeof pat, "\"%s\"", key);
+    const size_t plen = strlen(pat);
+    for (const char* p = obj; p + plen <= end; ++p) {
+        if (strncmp(p, pat, plen) != 0) continue;
+        p += plen;
+        while (p < end && (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r')) ++p;
+        if (p >= end || *p != ':') return false;
+        ++p;
+        char* q = nullptr;
+        v = strtol(p, &q, 10);
+        return q != p && q <= end;
+    }
+    return false;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ engine --
+
+namespace {
+
+// Device arena of a serving engine with K slots (multiple of 64), R request
+// entries and a staging area of SC points.
+struct EngLayout {
+    int64_t K, R, SC, scap, rcap;
+    size_t x[2], y[2], id[2], segs[2], seg_cid[2], vstart[2];
+    size_t bitmap, vidx, hout, recs, rec_cid, sets, gstart, sbase, bad, res_base, res_n, res_alive, res_h;
+    size_t stage, vlist, slots, ctab, bar, err, stats, sv, info;
+    size_t bytes;
+};
+
+bool make_eng_layout(int64_t K, int64_t R, int64_t SC, EngLayout& L)
+{
+    if (K < 64 || K % 64 || K > ((int64_t)INT32_MAX & ~63LL) - 64 || R < 1 || R > (1 << 20) || SC < 1 || SC > K)
+        return false;
+    L.K = K;
+    L.R = R;
+    L.SC = SC;
+    // every segment holds a point, a pass leaves at most 2/3 of its points
+    // in segments, and a new set adds at most 4 segments
+    L.scap = (2 * K) / 3 + 4 * R + 64;
+    L.rcap = std::max<int64_t>(4 * R, 2 * L.scap) + 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    for (int b = 0; b < 2; ++b) {
+        L.x[b] = take(sizeof(float) * (size_t)K);
+        L.y[b] = take(sizeof(float) * (size_t)K);
+        L.id[b] = take(sizeof(int) * (size_t)K);
+        L.segs[b] = take(sizeof(Seg) * (size_t)L.scap);
+        L.seg_cid[b] = take(sizeof(int) * (size_t)L.scap);
+        L.vstart[b] = take(sizeof(int) * (size_t)(L.scap + 1));
+    }
+    L.bitmap = take(sizeof(uint64_t) * (size_t)(K / 64));
+    L.vidx = take(sizeof(int) * (size_t)K);
+    L.hout = take(sizeof(int) * (size_t)K);
+    L.recs = take(sizeof(Seg) * (size_t)L.rcap);
+    L.rec_cid = take(sizeof(int) * (size_t)L.rcap);
+    L.sets = take(sizeof(SetInfo) * (size_t)R);
+    L.gstart = take(sizeof(int) * (size_t)(R + 1));
+    L.sbase = take(sizeof(int) * (size_t)R);
+    L.bad = take(sizeof(int) * (size_t)R);
+    L.res_base = take(sizeof(int) * (size_t)R);
+    L.res_n = take(sizeof(int) * (size_t)R);
+    L.res_alive = take(sizeof(int) * (size_t)R);
+    L.res_h = take(sizeof(int) * (size_t)R);
+    L.stage = take(sizeof(float2) * (size_t)SC);
+    L.vlist = take(sizeof(int2));
+    L.slots = take(sizeof(ChunkSlot<4>) * (size_t)kMaxGrid);
+    L.ctab = take(sizeof(Pair) * (size_t)kMaxGrid);
+    L.bar = take(sizeof(GridBar));
+    L.err = take(sizeof(int));
+    L.stats = take(sizeof(uint32_t) * 4 * kStatSlots);
+    L.sv = take(sizeof(int) * 4);
+    L.info = take(sizeof(HullInfo));
+    L.bytes = o;
+    return true;
+}
+
+struct EngReq {
+    uint64_t tag;
+    int64_t base, n, alloc, stage_at;
+};
+
+struct EngDone {
+    uint64_t tag;
+    int status;
+    std::vector<int32_t> hull;
+};
+
+}  // namespace
+
+struct sqh_engine {
+    sqh_ctx* ctx = nullptr;
+    char* arena = nullptr;
+    EngLayout L{};
+    int cur = 0;
+    bool broken = false;
+    std::map<int64_t, int64_t> free_ranges;  // first slot -> length (64-aligned)
+    std::vector<EngReq> staged, resident;
+    int64_t stage_used = 0;
+    std::deque<EngDone> done;
+    int* h_up = nullptr;     // pinned: gstart (R+1), sbase (R), res_base (R), res_n (R)
+    int* h_down = nullptr;   // pinned: res_alive (R), res_h (R), bad (R), err
+    int32_t* h_bounce = nullptr;
+    int64_t bounce_cap = 0;
+    HullInfo* h_info = nullptr;
+    int64_t steps = 0;
+};
+
+namespace {
+
+bool eng_alloc(sqh_engine* e, int64_t n, int64_t& base)
+{
+    const int64_t need = (n + 63) & ~63LL;
+    for (auto it = e->free_ranges.begin(); it != e->free_ranges.end(); ++it) {
+        if (it->second >= need) {
+            base = it->first;
+            const int64_t rest = it->second - need;
+            e->free_ranges.erase(it);
+            if (rest > 0) e->free_ranges[base + need] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void eng_free(sqh_engine* e, int64_t base, int64_t alloc)
+{
+    auto it = e->free_ranges.emplace(base, alloc).first;
+    auto next = std::next(it);
+    if (next != e->free_ranges.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        e->free_ranges.erase(next);
+    }
+    if (it != e->free_ranges.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            e->free_ranges.erase(it);
+        }
+    }
 }
 
 }  // namespace
@@ -231,12 +467,13 @@ int sqh_create(sqh_ctx** out, int device)
         delete c;
         return SQH_EDEVICE;
     }
-    c->grid = std::min(kMaxGrid, per_cu * c->cus);
+    c->max_grid = std::min(kMaxGrid, per_cu * c->cus);
     {
         const char* t = getenv("SQH_TRACE");
         c->trace = t && t[0] == '1';
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->evk) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->hstats), sizeof(uint32_t) * 4 * kStatSlots,
                       hipHostMallocDefault) != hipSuccess ||
@@ -252,6 +489,7 @@ void sqh_destroy(sqh_ctx* c)
 {
     if (!c) return;
     if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->evk) (void)hipEventDestroy(c->evk);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->hinfo) (void)hipHostFree(c->hinfo);
     if (c->hstats) (void)hipHostFree(c->hstats);
@@ -292,11 +530,463 @@ int sqh_hull_batched(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
                static_cast<hipStream_t>(stream));
 }
 
+int sqh_autotune(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, int64_t n_sets, int64_t n_total,
+                 int32_t* d_out, int64_t* d_out_off, int64_t out_cap, void* d_ws, size_t ws_bytes, void* stream,
+                 int reps)
+{
+    if (!c || n_sets < 1 || n_total < 0 || reps < 1 || reps > 100) return SQH_EINVAL;
+    if (n_sets > 1 && (!d_set_off || !d_out_off)) return SQH_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int cls = log2_class(n_total);
+    const int m = c->max_grid;
+    const int grids[4] = {m, std::max(1, (3 * m) / 4), std::max(1, m / 2), std::max(1, m / 4)};
+    const int tails[3] = {1 << 14, 1 << 16, 1 << 18};
+    TuneEntry best{cls, m, kTailPoints};
+    double best_ms = 1e300;
+    int64_t h = 0;
+    for (int gi = 0; gi < 4; ++gi) {
+        if (gi > 0 && grids[gi] == grids[gi - 1]) continue;
+        for (int ti = 0; ti < 3; ++ti) {
+            const TuneEntry tu{cls, grids[gi], tails[ti]};
+            int rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes,
+                               st, tu);  // warm-up
+            if (rc != SQH_OK) return rc;
+            double t[100];
+            for (int r = 0; r < reps; ++r) {
+                rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes,
+                               st, tu);
+                if (rc != SQH_OK) return rc;
+                t[r] = c->stats.ms_total;
+            }
+            std::sort(t, t + reps);
+            const double med = t[reps / 2];
+            if (med < best_ms) {
+                best_ms = med;
+                best = tu;
+            }
+        }
+    }
+    int slot = -1;
+    for (int i = 0; i < c->ntune; ++i)
+        if (c->tune[i].log2n == cls) slot = i;
+    if (slot < 0) {
+        if (c->ntune >= sqh_ctx::kMaxTune) return SQH_ENOMEM;
+        slot = c->ntune++;
+    }
+    c->tune[slot] = best;
+    return SQH_OK;
+}
+
+int sqh_get_tuning(const sqh_ctx* c, char* buf, size_t len)
+{
+    if (!c) return SQH_EINVAL;
+    char tmp[64 * sqh_ctx::kMaxTune + 64];
+    int n = snprintf(tmp, sizeof tmp, "{\"entries\": [");
+    for (int i = 0; i < c->ntune; ++i)
+        n += snprintf(tmp + n, sizeof tmp - n, "%s{\"log2n\": %d, \"grid\": %d, \"tail\": %d}", i ? ", " : "",
+                      c->tune[i].log2n, c->tune[i].grid, c->tune[i].tail);
+    n += snprintf(tmp + n, sizeof tmp - n, "]}");
+    if (buf && len > 0) {
+        const size_t k = std::min<size_t>(len - 1, (size_t)n);
+        memcpy(buf, tmp, k);
+        buf[k] = 0;
+    }
+    return n + 1;
+}
+
+int sqh_set_tuning(sqh_ctx* c, const char* json)
+{
+    if (!c || !json) return SQH_EINVAL;
+    TuneEntry t[sqh_ctx::kMaxTune];
+    int nt = 0;
+    const char* p = strstr(json, "\"entries\"");
+    if (!p) return SQH_EINVAL;
+    p = strchr(p, '[');
+    if (!p) return SQH_EINVAL;
+    const char* close = strchr(p, ']');
+    if (!close) return SQH_EINVAL;
+    for (const char* o = strchr(p, '{'); o && o < close; o = strchr(o + 1, '{')) {
+        const char* e = strchr(o, '}');
+        if (!e || e > close) return SQH_EINVAL;
+        long k = 0, g = 0, tl = 0;
+        if (!read_int_key(o, e, "log2n", k) || !read_int_key(o, e, "grid", g) || !read_int_key(o, e, "tail", tl))
+            return SQH_EINVAL;
+        if (k < 0 || k > 62 || g < 1 || g > c->max_grid || tl < 0 || tl > INT32_MAX) return SQH_EINVAL;
+        if (nt >= sqh_ctx::kMaxTune) return SQH_EINVAL;
+        t[nt++] = TuneEntry{(int)k, (int)g, (int)tl};
+    }
+    memcpy(c->tune, t, sizeof(TuneEntry) * nt);
+    c->ntune = nt;
+    return SQH_OK;
+}
+
+int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, int64_t n_sets, int64_t n_total,
+                     int32_t* d_out, int64_t* d_out_off, int64_t out_cap, void* d_ws, size_t ws_bytes,
+                     sqh_graph** out)
+{
+    if (!out) return SQH_EINVAL;
+    *out = nullptr;
+    if (!c || n_sets < 1 || n_total < 0) return SQH_EINVAL;
+    if (n_sets > 1 && (!d_set_off || !d_out_off)) return SQH_EINVAL;
+    sqh_graph* g = new (std::nothrow) sqh_graph();
+    if (!g) return SQH_ENOMEM;
+    g->ctx = c;
+    g->N = n_total;
+    g->out_cap = out_cap;
+    const TuneEntry tu = pick_tuning(c, n_total);
+    int reset_grid = 1;
+    int rc = setup(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, d_ws, ws_bytes, tu, g->args,
+                   reset_grid);
+    if (rc != SQH_OK) {
+        delete g;
+        return rc;
+    }
+    // two kernel nodes: the workspace reset, then the persistent kernel,
+    // marked cooperative so that every workgroup is resident at once
+    hipGraphNode_t n_reset = nullptr, n_hull = nullptr;
+    void* argv[] = {static_cast<void*>(&g->args)};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(k_reset);
+    kp.gridDim = dim3(reset_grid);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = argv;
+    kp.extra = nullptr;
+    hipKernelNodeParams hp = kp;
+    hp.func = reinterpret_cast<void*>(k_hull);
+    hp.gridDim = dim3(tu.grid);
+    hp.blockDim = dim3(kBlock);
+    hipKernelNodeAttrValue coop{};
+    coop.cooperative = 1;
+    if (hipGraphCreate(&g->graph, 0) != hipSuccess ||
+        hipGraphAddKernelNode(&n_reset, g->graph, nullptr, 0, &kp) != hipSuccess ||
+        hipGraphAddKernelNode(&n_hull, g->graph, &n_reset, 1, &hp) != hipSuccess ||
+        hipGraphKernelNodeSetAttribute(n_hull, hipKernelNodeAttributeCooperative, &coop) != hipSuccess ||
+        hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        sqh_graph_destroy(g);
+        return SQH_EDEVICE;
+    }
+    *out = g;
+    return SQH_OK;
+}
+
+int sqh_graph_launch(sqh_graph* g, void* stream)
+{
+    if (!g || !g->exec) return SQH_EINVAL;
+    HIP_OK(hipSetDevice(g->ctx->device));
+    HIP_OK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return SQH_OK;
+}
+
+int sqh_graph_result(sqh_graph* g, int64_t* h_total, void* stream)
+{
+    if (!g || !g->exec) return SQH_EINVAL;
+    HIP_OK(hipSetDevice(g->ctx->device));
+    return collect(g->ctx, g->args, g->N, g->out_cap, h_total, static_cast<hipStream_t>(stream), false);
+}
+
+void sqh_graph_destroy(sqh_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+size_t sqh_engine_bytes(int64_t slots, int64_t max_requests, int64_t stage_points)
+{
+    EngLayout L;
+    if (!make_eng_layout(slots, max_requests, stage_points, L)) return 0;
+    return L.bytes;
+}
+
+int sqh_engine_create(sqh_ctx* c, void* d_arena, size_t arena_bytes, int64_t slots, int64_t max_requests,
+                      int64_t stage_points, sqh_engine** out)
+{
+    if (!out) return SQH_EINVAL;
+    *out = nullptr;
+    if (!c || !d_arena) return SQH_EINVAL;
+    EngLayout L;
+    if (!make_eng_layout(slots, max_requests, stage_points, L)) return SQH_EINVAL;
+    if (arena_bytes < L.bytes) return SQH_ENOMEM;
+    HIP_OK(hipSetDevice(c->device));
+    sqh_engine* e = new (std::nothrow) sqh_engine();
+    if (!e) return SQH_ENOMEM;
+    e->ctx = c;
+    e->arena = static_cast<char*>(d_arena);
+    e->L = L;
+    e->free_ranges[0] = slots;
+    const size_t up = sizeof(int) * (size_t)(4 * max_requests + 1);
+    const size_t down = sizeof(int) * (size_t)(3 * max_requests + 1);
+    e->bounce_cap = 1 << 20;
+    if (hipHostMalloc(reinterpret_cast<void**>(&e->h_up), up, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&e->h_down), down, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&e->h_bounce), sizeof(int32_t) * (size_t)e->bounce_cap,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&e->h_info), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess) {
+        sqh_engine_destroy(e);
+        return SQH_EDEVICE;
+    }
+    // empty resident tables in both survivor buffers
+    if (hipMemset(e->arena + L.sv, 0, sizeof(int) * 4) != hipSuccess ||
+        hipMemset(e->arena + L.vstart[0], 0, sizeof(int)) != hipSuccess ||
+        hipMemset(e->arena + L.vstart[1], 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        sqh_engine_destroy(e);
+        return SQH_EDEVICE;
+    }
+    *out = e;
+    return SQH_OK;
+}
+
+void sqh_engine_destroy(sqh_engine* e)
+{
+    if (!e) return;
+    if (e->h_up) (void)hipHostFree(e->h_up);
+    if (e->h_down) (void)hipHostFree(e->h_down);
+    if (e->h_bounce) (void)hipHostFree(e->h_bounce);
+    if (e->h_info) (void)hipHostFree(e->h_info);
+    delete e;
+}
+
+int sqh_engine_admit(sqh_engine* e, const float* xy, int64_t n, uint64_t tag, int on_device, void* stream)
+{
+    if (!e || n < 0 || (n > 0 && !xy)) return SQH_EINVAL;
+    if (e->broken) return SQH_EDEVICE;
+    if (n > e->L.SC || n > e->L.K) return SQH_EINVAL;  // can never fit
+    if (n == 0) {
+        e->done.push_back(EngDone{tag, SQH_OK, {}});
+        return SQH_OK;
+    }
+    if ((int64_t)(e->staged.size() + e->resident.size()) >= e->L.R) return SQH_EBUSY;
+    if (e->stage_used + n > e->L.SC) return SQH_EBUSY;
+    int64_t base = 0;
+    if (!eng_alloc(e, n, base)) return SQH_EBUSY;
+    HIP_OK(hipSetDevice(e->ctx->device));
+    float2* stage = reinterpret_cast<float2*>(e->arena + e->L.stage) + e->stage_used;
+    if (hipMemcpyAsync(stage, xy, sizeof(float2) * (size_t)n,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream)) != hipSuccess) {
+        eng_free(e, base, (n + 63) & ~63LL);
+        return SQH_EDEVICE;
+    }
+    e->staged.push_back(EngReq{tag, base, n, (n + 63) & ~63LL, e->stage_used});
+    e->stage_used += n;
+    return SQH_OK;
+}
+
+int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
+{
+    if (!e || max_passes < 1 || max_passes > kMaxPasses) return SQH_EINVAL;
+    if (e->broken) return SQH_EDEVICE;
+    if (e->staged.empty() && e->resident.empty()) return 0;
+    sqh_ctx* c = e->ctx;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_OK(hipSetDevice(c->device));
+    const EngLayout& L = e->L;
+    const int64_t R = L.R;
+    const int G = (int)e->staged.size();
+    // all requests in slot order (new ones included) for the census
+    std::vector<EngReq> all(e->resident);
+    all.insert(all.end(), e->staged.begin(), e->staged.end());
+    std::sort(all.begin(), all.end(), [](const EngReq& p, const EngReq& q) { return p.base < q.base; });
+    const int nres = (int)all.size();
+    int* up_gstart = e->h_up;
+    int* up_sbase = e->h_up + (R + 1);
+    int* up_rbase = e->h_up + (2 * R + 1);
+    int* up_rn = e->h_up + (3 * R + 1);
+    for (int g = 0; g < G; ++g) {
+        up_gstart[g] = (int)e->staged[g].stage_at;
+        up_sbase[g] = (int)e->staged[g].base;
+    }
+    up_gstart[G] = (int)e->stage_used;
+    for (int r = 0; r < nres; ++r) {
+        up_rbase[r] = (int)all[r].base;
+        up_rn[r] = (int)all[r].n;
+    }
+    char* A = e->arena;
+    auto at = [&](size_t off) { return static_cast<void*>(A + off); };
+    HIP_OK(hipMemcpyAsync(at(L.gstart), up_gstart, sizeof(int) * (size_t)(G + 1), hipMemcpyHostToDevice, st));
+    if (G > 0) HIP_OK(hipMemcpyAsync(at(L.sbase), up_sbase, sizeof(int) * (size_t)G, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(at(L.res_base), up_rbase, sizeof(int) * (size_t)nres, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(at(L.res_n), up_rn, sizeof(int) * (size_t)nres, hipMemcpyHostToDevice, st));
+
+    const TuneEntry tu = pick_tuning(c, e->stage_used > 0 ? e->stage_used : 1);
+    HullArgs a{};
+    a.xy = static_cast<const float2*>(at(L.stage));
+    a.N = (int)e->stage_used;
+    a.G = G;
+    for (int b = 0; b < 2; ++b) {
+        a.X[b] = static_cast<float*>(at(L.x[b]));
+        a.Y[b] = static_cast<float*>(at(L.y[b]));
+        a.I[b] = static_cast<int*>(at(L.id[b]));
+        a.segs[b] = static_cast<Seg*>(at(L.segs[b]));
+        a.seg_cid[b] = static_cast<int*>(at(L.seg_cid[b]));
+        a.vstart[b] = static_cast<int*>(at(L.vstart[b]));
+    }
+    a.gstart = static_cast<int*>(at(L.gstart));
+    a.sets = static_cast<SetInfo*>(at(L.sets));
+    a.recs = static_cast<Seg*>(at(L.recs));
+    a.rec_cid = static_cast<int*>(at(L.rec_cid));
+    a.sv = static_cast<int*>(at(L.sv));
+    a.bitmap = static_cast<uint64_t*>(at(L.bitmap));
+    a.vidx = static_cast<int*>(at(L.vidx));
+    a.vlist = static_cast<int2*>(at(L.vlist));
+    a.vcap = 0;
+    a.slots = at(L.slots);
+    a.ctab = static_cast<Pair*>(at(L.ctab));
+    a.bar = static_cast<GridBar*>(at(L.bar));
+    a.err = static_cast<int*>(at(L.err));
+    a.stats = static_cast<uint32_t*>(at(L.stats));
+    a.info = static_cast<HullInfo*>(at(L.info));
+    a.fp64 = c->fp64;
+    a.timing = 1;
+    a.tail_points = tu.tail;
+    a.sbase = static_cast<const int*>(at(L.sbase));
+    a.cur0 = e->cur;
+    a.max_passes = max_passes;
+    a.nres = nres;
+    a.res_base = static_cast<const int*>(at(L.res_base));
+    a.res_n = static_cast<const int*>(at(L.res_n));
+    a.res_alive = static_cast<int*>(at(L.res_alive));
+    a.res_h = static_cast<int*>(at(L.res_h));
+    a.hout = static_cast<int*>(at(L.hout));
+    a.bad = static_cast<int*>(at(L.bad));
+
+    HIP_OK(hipEventRecord(c->ev0, st));
+    k_engine_reset<<<std::max(1, std::min(1024, std::max(G, nres / 256 + 1))), 256, 0, st>>>(a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(c->evk, st));
+    void* argv[] = {static_cast<void*>(&a)};
+    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_engine_step), dim3(tu.grid), dim3(kBlock),
+                                      argv, 0, st));
+    HIP_OK(hipEventRecord(c->ev1, st));
+    int* dn_alive = e->h_down;
+    int* dn_h = e->h_down + R;
+    int* dn_bad = e->h_down + 2 * R;
+    int* dn_err = e->h_down + 3 * R;
+    HIP_OK(hipMemcpyAsync(dn_alive, at(L.res_alive), sizeof(int) * (size_t)nres, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(dn_h, at(L.res_h), sizeof(int) * (size_t)nres, hipMemcpyDeviceToHost, st));
+    if (G > 0) HIP_OK(hipMemcpyAsync(dn_bad, at(L.bad), sizeof(int) * (size_t)G, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(dn_err, at(L.err), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(e->h_info, at(L.info), offsetof(HullInfo, trace), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(c->hstats, at(L.stats), sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (*dn_err & (kErrSpin | kErrBounds)) {
+        e->broken = true;
+        return SQH_EDEVICE;
+    }
+    e->cur = e->h_info->cur_out;
+    ++e->steps;
+    {
+        sqh_stats& S = c->stats;
+        S = sqh_stats{};
+        S.points = e->stage_used;
+        S.passes = e->h_info->passes;
+        for (int i = 0; i < kStatSlots; ++i) {
+            S.orient_evals += c->hstats[4 * i + 0];
+            S.orient_exact += c->hstats[4 * i + 1];
+            S.cmp_exact += c->hstats[4 * i + 2];
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) S.ms_total = ms;
+        if (hipEventElapsedTime(&ms, c->evk, c->ev1) == hipSuccess) S.ms_kernel = ms;
+    }
+    // bad inputs among the new requests (their sets were skipped)
+    std::map<int64_t, int> bad_base;
+    for (int g = 0; g < G; ++g)
+        if (dn_bad[g]) bad_base[e->staged[g].base] = 1;
+    // collect finished requests: copy their hulls through the pinned bounce buffer
+    int finished = 0;
+    std::vector<EngReq> keep;
+    std::vector<std::pair<EngReq, int>> fin;
+    for (int r = 0; r < nres; ++r) {
+        if (dn_alive[r]) keep.push_back(all[r]);
+        else fin.push_back({all[r], dn_h[r]});
+    }
+    size_t i0 = 0;
+    while (i0 < fin.size()) {
+        int64_t used = 0;
+        size_t i1 = i0;
+        while (i1 < fin.size() && (i1 == i0 || used + fin[i1].second <= e->bounce_cap)) {
+            const int h = fin[i1].second;
+            if (h > e->bounce_cap) break;  // (cannot happen: h <= n <= stage capacity... checked below)
+            if (h > 0)
+                HIP_OK(hipMemcpyAsync(e->h_bounce + used, A + L.hout + sizeof(int) * (size_t)fin[i1].first.base,
+                                      sizeof(int) * (size_t)h, hipMemcpyDeviceToHost, st));
+            used += h;
+            ++i1;
+        }
+        if (i1 == i0) {
+            // one hull larger than the bounce buffer: copy it directly
+            const EngReq& q = fin[i0].first;
+            EngDone d{q.tag, SQH_OK, std::vector<int32_t>((size_t)fin[i0].second)};
+            HIP_OK(hipMemcpy(d.hull.data(), A + L.hout + sizeof(int) * (size_t)q.base,
+                             sizeof(int) * (size_t)fin[i0].second, hipMemcpyDeviceToHost));
+            if (bad_base.count(q.base)) { d.status = SQH_EINVAL; d.hull.clear(); }
+            e->done.push_back(std::move(d));
+            eng_free(e, q.base, q.alloc);
+            ++finished;
+            ++i0;
+            continue;
+        }
+        HIP_OK(hipStreamSynchronize(st));
+        int64_t off = 0;
+        for (size_t i = i0; i < i1; ++i) {
+            const EngReq& q = fin[i].first;
+            const int h = fin[i].second;
+            EngDone d{q.tag, SQH_OK, std::vector<int32_t>(e->h_bounce + off, e->h_bounce + off + h)};
+            if (bad_base.count(q.base)) { d.status = SQH_EINVAL; d.hull.clear(); }
+            e->done.push_back(std::move(d));
+            off += h;
+            eng_free(e, q.base, q.alloc);
+            ++finished;
+        }
+        i0 = i1;
+    }
+    e->resident.swap(keep);
+    e->staged.clear();
+    e->stage_used = 0;
+    return finished;
+}
+
+int sqh_engine_poll(sqh_engine* e, uint64_t* tag, int32_t* h_out, int64_t cap, int64_t* h)
+{
+    if (!e || !tag || !h || cap < 0 || (cap > 0 && !h_out)) return SQH_EINVAL;
+    if (e->done.empty()) return SQH_ENOTFOUND;
+    EngDone& d = e->done.front();
+    *tag = d.tag;
+    *h = (int64_t)d.hull.size();
+    const int st = d.status;
+    if (st != SQH_OK) {
+        e->done.pop_front();
+        return st;
+    }
+    if (*h > cap) return SQH_ECAPACITY;  // kept: poll again with a larger buffer
+    if (*h > 0) memcpy(h_out, d.hull.data(), sizeof(int32_t) * (size_t)*h);
+    e->done.pop_front();
+    return SQH_OK;
+}
+
+int sqh_engine_status(const sqh_engine* e, int64_t* resident, int64_t* staged, int64_t* finished,
+                      int64_t* free_slots)
+{
+    if (!e) return SQH_EINVAL;
+    if (resident) *resident = (int64_t)e->resident.size();
+    if (staged) *staged = (int64_t)e->staged.size();
+    if (finished) *finished = (int64_t)e->done.size();
+    if (free_slots) {
+        int64_t f = 0;
+        for (const auto& kv : e->free_ranges) f += kv.second;
+        *free_slots = f;
+    }
+    return e->broken ? SQH_EDEVICE : SQH_OK;
+}
+
 int sqh_get_trace(const sqh_ctx* c, uint64_t* out, int max_entries)
 {
     if (!c || !out || max_entries < 0) return SQH_EINVAL;
     if (!c->trace) return 0;
-    const int n = std::min(max_entries, c->grid * 8);
+    const int n = std::min(max_entries, c->max_grid * 8);
     for (int i = 0; i < n; ++i) out[i] = c->hinfo->trace[i / 8][i % 8];
     return n;
 }

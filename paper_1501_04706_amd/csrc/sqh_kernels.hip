@@ -52,7 +52,7 @@ __device__ __forceinline__ void record_vertex(uint64_t* bitmap, int* vidx, int2*
 // ============================================================ k_seed ==
 struct PolSeed {
     static constexpr int NB = 2;
-    static constexpr bool COUNTS = false, SCATTER = false, MULTI = true;
+    static constexpr bool COUNTS = false, SCATTER = false, MULTI = true, MIDDLE = false;
     static constexpr int ROWS = kRows;
     struct Ctx {
         int base;
@@ -61,6 +61,7 @@ struct PolSeed {
     const int* gstart;
     SetInfo* sets;
     int* err;
+    int* bad;  // null, or one flag per set raised by a non-finite coordinate
     int G;
 
     __device__ __forceinline__ int num_groups() const { return G; }
@@ -73,10 +74,11 @@ struct PolSeed {
         const float2 v = gld(xy + q);
         x = v.x; y = v.y; id = q - c.base;
     }
-    __device__ __forceinline__ int classify(const Ctx&, int, int q, float x, float y, int id, Cand& k, Counters&) const
+    __device__ __forceinline__ int classify(const Ctx&, int g, int q, float x, float y, int id, Cand& k, Counters&) const
     {
         if (!(isfinite(x) && isfinite(y))) {
             atomicOr(err, kErrNonFinite);
+            if (bad) bad[g] = 1;
             return 0;
         }
         k.a = 0.0f; k.w = 0.0f; k.x = x; k.y = y; k.id = id;
@@ -111,14 +113,16 @@ struct PolSeed {
 // =========================================================== k_split ==
 struct PolSplit {
     static constexpr int NB = 2;
-    static constexpr bool COUNTS = true, SCATTER = false, MULTI = false;
+    static constexpr bool COUNTS = true, SCATTER = false, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
     struct Ctx {
         Edge ab, ba;
-        int base, skip;
+        int base, sbase, skip;  // first read position, first slot (vertex keys)
     };
     const float2* xy;
     const int* gstart;
+    const int* sbase;
+    const int* bad;  // null, or sets to skip (non-finite input)
     SetInfo* sets;
     uint64_t* bitmap;
     int* vidx;
@@ -138,8 +142,9 @@ struct PolSplit {
         c.ab = make_edge(s.ax, s.ay, s.bx, s.by);
         c.ba = make_edge(s.bx, s.by, s.ax, s.ay);
         c.base = gld(gstart + g);
+        c.sbase = gld(sbase + g);
         // lexmin and lexmax coincide only if every point sits at one position
-        c.skip = (s.ax == s.bx) && (s.ay == s.by);
+        c.skip = ((s.ax == s.bx) && (s.ay == s.by)) || (bad && gld(bad + g));
         return c;
     }
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
@@ -181,8 +186,8 @@ struct PolSplit {
         s.cux = a.best[1].x; s.cuy = a.best[1].y; s.cuid = a.best[1].id;
         gst(sets + g, s);
         // vertex keys: A at the set's first slot, B right after the lower side
-        record_vertex(bitmap, vidx, vlist, info, c.base, s.aid);
-        if (!c.skip) record_vertex(bitmap, vidx, vlist, info, c.base + 1 + a.cnt[0], s.bid);
+        record_vertex(bitmap, vidx, vlist, info, c.sbase, s.aid);
+        if (!c.skip) record_vertex(bitmap, vidx, vlist, info, c.sbase + 1 + a.cnt[0], s.bid);
     }
 };
 
@@ -196,15 +201,17 @@ struct PolSplit {
 //   [base+2+n_lo, base+2+n_lo+n_up)    upper side: (B,C_up) front, (C_up,A) back
 struct PolFirst {
     static constexpr int NB = 4;
-    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false;
+    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
     struct Ctx {
         Edge ab;
         Edge e[4];  // A->C_lo, C_lo->B, B->C_up, C_up->A
-        int base, n_lo, n_up, skip;
+        int base, sbase, n_lo, n_up, skip;  // first read position, first slot
     };
     const float2* xy;
     const int* gstart;
+    const int* sbase;
+    const int* bad;
     const SetInfo* sets;
     float* X;
     float* Y;
@@ -232,9 +239,10 @@ struct PolFirst {
         c.e[2] = make_edge(s.bx, s.by, s.cux, s.cuy);
         c.e[3] = make_edge(s.cux, s.cuy, s.ax, s.ay);
         c.base = gld(gstart + g);
+        c.sbase = gld(sbase + g);
         c.n_lo = s.n_lo;
         c.n_up = s.n_up;
-        c.skip = (s.ax == s.bx) && (s.ay == s.by);
+        c.skip = ((s.ax == s.bx) && (s.ay == s.by)) || (bad && gld(bad + g));
         return c;
     }
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
@@ -278,10 +286,10 @@ struct PolFirst {
     __device__ __forceinline__ int place(const Ctx& c, int, int k, int rank) const
     {
         switch (k) {
-        case 0: return c.base + 1 + rank;
-        case 1: return c.base + c.n_lo - rank;
-        case 2: return c.base + 2 + c.n_lo + rank;
-        default: return c.base + 1 + c.n_lo + c.n_up - rank;
+        case 0: return c.sbase + 1 + rank;
+        case 1: return c.sbase + c.n_lo - rank;
+        case 2: return c.sbase + 2 + c.n_lo + rank;
+        default: return c.sbase + 1 + c.n_lo + c.n_up - rank;
         }
     }
     __device__ __forceinline__ void store(int dst, float x, float y, int id) const
@@ -301,14 +309,14 @@ struct PolFirst {
     {
         const SetInfo s = gld(sets + g);
         if (c.n_lo > 0) {
-            record_vertex(bitmap, vidx, vlist, info, c.base + 1 + a.cnt[0], s.clid);
-            child(4 * g + 0, c.e[0], a.best[0], c.base + 1, a.cnt[0]);
-            child(4 * g + 1, c.e[1], a.best[1], c.base + 1 + c.n_lo - a.cnt[1], a.cnt[1]);
+            record_vertex(bitmap, vidx, vlist, info, c.sbase + 1 + a.cnt[0], s.clid);
+            child(4 * g + 0, c.e[0], a.best[0], c.sbase + 1, a.cnt[0]);
+            child(4 * g + 1, c.e[1], a.best[1], c.sbase + 1 + c.n_lo - a.cnt[1], a.cnt[1]);
         }
         if (c.n_up > 0) {
-            record_vertex(bitmap, vidx, vlist, info, c.base + 2 + c.n_lo + a.cnt[2], s.cuid);
-            child(4 * g + 2, c.e[2], a.best[2], c.base + 2 + c.n_lo, a.cnt[2]);
-            child(4 * g + 3, c.e[3], a.best[3], c.base + 2 + c.n_lo + c.n_up - a.cnt[3], a.cnt[3]);
+            record_vertex(bitmap, vidx, vlist, info, c.sbase + 2 + c.n_lo + a.cnt[2], s.cuid);
+            child(4 * g + 2, c.e[2], a.best[2], c.sbase + 2 + c.n_lo, a.cnt[2]);
+            child(4 * g + 3, c.e[3], a.best[3], c.sbase + 2 + c.n_lo + c.n_up - a.cnt[3], a.cnt[3]);
         }
     }
 };
@@ -320,7 +328,9 @@ struct PolFirst {
 // key is the first slot after the (A,C) points.
 struct PolPass {
     static constexpr int NB = 2;
-    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false;
+    // MIDDLE: groups are never empty, so rows holding whole groups take the
+    // lane-parallel path
+    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = true;
     static constexpr int ROWS = kRows;
     struct Ctx {
         Edge e[2];  // A->C, C->B
@@ -516,7 +526,7 @@ constexpr int kMaxChunks = 512;  // workgroups of the persistent grid (upper bou
 constexpr int kMaxInfoPasses = 256;
 constexpr int kMaxPasses = 1 << 16;
 constexpr int kMaxStamps = 1024;
-constexpr int kTailPoints = 1 << 16;   // below this many points one workgroup finishes the passes
+constexpr int kTailPoints = 1 << 16;   // default: below this many points one workgroup finishes the passes
 constexpr int kSmallHull = 2048;       // single hulls up to this size are emitted by one workgroup
 
 // info block written for the host
@@ -526,6 +536,7 @@ struct HullInfo {
     int first_v;
     int vcount;
     int vcap;     // capacity of the vertex list
+    int cur_out;  // engine: survivor buffer holding the segments left after the step
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -566,6 +577,18 @@ struct HullArgs {
     int fp64;
     int timing;
     int vcap;
+    int tail_points;         // passes over at most this many points run on workgroup 0 alone
+    // serving engine (k_engine_step); k_hull uses sbase = gstart, cur0 = 0
+    const int* sbase;        // G: first slot of each new set (read positions start at gstart)
+    int cur0;                // survivor buffer (0/1) holding the resident segments
+    int max_passes;          // passes in this step
+    int nres;                // resident sets, sorted by first slot
+    const int* res_base;     // nres: first slot
+    const int* res_n;        // nres: points
+    int* res_alive;          // nres: set if the set still has a segment after the step
+    int* res_h;              // nres: hull size of a set finished in this step
+    int* hout;               // slot-indexed hull output of finished sets
+    int* bad;                // G: new set had a non-finite coordinate
 };
 
 __device__ __forceinline__ void stamp(const HullArgs& a, int tag)
@@ -769,10 +792,12 @@ __device__ __forceinline__ void phase_step_b(const HullArgs& a, const Pol& pol, 
 // it ends here, compact the child records of the groups finalised by this
 // chunk into the next segment table, then write the chunk's points to their
 // child segments.
+// The new table is written after tb.a entries holding tb.b positions
+// (segments already in the table stay in place).
 template <class Pol>
 __device__ __forceinline__ void phase_step_bc(const HullArgs& a, const Pol& pol, int P, int nb, int b, int mul,
                                               int glo, int ghi, Seg* segs, int* seg_cid, int* vstart, int* sv,
-                                              ChunkShared<Pol>& sh, Pair* red, Counters& ctr)
+                                              Pair tb, ChunkShared<Pol>& sh, Pair* red, Counters& ctr)
 {
     auto* slots = reinterpret_cast<ChunkSlot<Pol::NB>*>(a.slots);
     const int CH = chunk_len(P, nb);
@@ -780,11 +805,11 @@ __device__ __forceinline__ void phase_step_bc(const HullArgs& a, const Pol& pol,
     const int nonempty = (P + CH - 1) / CH;
     __shared__ ScanOut<Pol::NB> so;
     slot_scan<Pol>(slots, b, nonempty, *reinterpret_cast<ScanLds<Pol::NB>*>(g_summ), so, red);
-    Pair at = so.tab_before;
+    Pair at = {tb.a + so.tab_before.a, tb.b + so.tab_before.b};
     if (b >= nonempty) {
         // empty chunk: only the last workgroup has a job, the table totals
         if (b == nb - 1 && threadIdx.x == 0) {
-            const Pair tot = {so.tab_before.a + so.tab_self.a, so.tab_before.b + so.tab_self.b};
+            const Pair tot = {at.a + so.tab_self.a, at.b + so.tab_self.b};
             sv[0] = tot.a;
             sv[1] = tot.b;
             vstart[tot.a] = tot.b;
@@ -842,15 +867,15 @@ __device__ __forceinline__ void phase_reduce(const HullArgs& a, const Pol& pol, 
 // A compaction phase: on the whole grid, or (SINGLE) on workgroup 0 alone.
 template <class Pol, bool SINGLE>
 __device__ __forceinline__ void phase_compact(const HullArgs& a, const Pol& pol, int P, int mul, Seg* segs,
-                                              int* seg_cid, int* vstart, int* sv, ChunkShared<Pol>& sh, Pair* red,
-                                              Counters& ctr)
+                                              int* seg_cid, int* vstart, int* sv, Pair tb, ChunkShared<Pol>& sh,
+                                              Pair* red, Counters& ctr)
 {
     const int nb = SINGLE ? 1 : (int)gridDim.x, b = SINGLE ? 0 : (int)blockIdx.x;
     int glo, ghi;
     phase_step_a(a, pol, P, nb, b, mul, sh, red, ctr, glo, ghi);
     if (SINGLE) __syncthreads();
     else grid_sync(a.bar, a.err);
-    phase_step_bc(a, pol, P, nb, b, mul, glo, ghi, segs, seg_cid, vstart, sv, sh, red, ctr);
+    phase_step_bc(a, pol, P, nb, b, mul, glo, ghi, segs, seg_cid, vstart, sv, tb, sh, red, ctr);
     if (SINGLE) __syncthreads();
     else grid_sync(a.bar, a.err);
 }
@@ -862,8 +887,8 @@ __device__ __forceinline__ void run_pass(const HullArgs& a, int cur, int S, int 
     const int nxt = cur ^ 1;
     PolPass pol{a.segs[cur], a.seg_cid[cur], a.vstart[cur], a.X[cur], a.Y[cur], a.I[cur], a.X[nxt], a.Y[nxt],
                 a.I[nxt], a.recs, a.rec_cid, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, S};
-    phase_compact<PolPass, SINGLE>(a, pol, V, 2, a.segs[nxt], a.seg_cid[nxt], a.vstart[nxt], a.sv + 2 * nxt, sh, red,
-                                   ctr);
+    phase_compact<PolPass, SINGLE>(a, pol, V, 2, a.segs[nxt], a.seg_cid[nxt], a.vstart[nxt], a.sv + 2 * nxt,
+                                   Pair{0, 0}, sh, red, ctr);
 }
 
 __device__ __forceinline__ void note_pass(const HullArgs& a, int pass, int S, int V)
@@ -963,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     if (ld_flag(a.err) & kErrBounds) goto done;  // set offsets rejected by k_reset
     // ---- seed: lexmin / lexmax of every set
     {
-        PolSeed pol{a.xy, a.gstart, a.sets, a.err, a.G};
+        PolSeed pol{a.xy, a.gstart, a.sets, a.err, nullptr, a.G};
         phase_reduce(a, pol, a.N, shS, red, ctr);
     }
     stamp(a, 1);
@@ -971,15 +996,16 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;
     // ---- first split: side counts and farthest point of each side
     {
-        PolSplit pol{a.xy, a.gstart, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, a.G};
+        PolSplit pol{a.xy, a.gstart, a.gstart, nullptr, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, a.G};
         phase_reduce(a, pol, a.N, shP, red, ctr);
     }
     stamp(a, 2);
     // ---- first compaction into four child segments per set
     {
-        PolFirst pol{a.xy, a.gstart, a.sets, a.X[0], a.Y[0], a.I[0], a.recs, a.rec_cid, a.bitmap, a.vidx,
-                     a.vlist, a.info, a.fp64, a.G};
-        phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, shF, red, ctr);
+        PolFirst pol{a.xy,     a.gstart,  a.gstart, nullptr, a.sets, a.X[0], a.Y[0], a.I[0], a.recs,
+                     a.rec_cid, a.bitmap, a.vidx,   a.vlist, a.info, a.fp64, a.G};
+        phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, Pair{0, 0}, shF,
+                                       red, ctr);
     }
     stamp(a, 3);
     // ---- segmented passes over all segments of all sets
@@ -993,7 +1019,7 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
                 if (b == 0 && threadIdx.x == 0) atomicOr(a.err, kErrBounds);
                 break;
             }
-            if (V <= kTailPoints) {
+            if (V <= a.tail_points) {
                 // few points left: workgroup 0 finishes the passes alone
                 tail = true;
                 if (b == 0) {

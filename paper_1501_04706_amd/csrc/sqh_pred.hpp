@@ -160,10 +160,34 @@ __device__ __forceinline__ int expansion_sign(const double (&t)[K])
     return sg;
 }
 
-// sign of orient(o, e, p), exactly:
+// float64 stage. With float32 inputs, each difference fl64(q - o) has a
+// relative error of at most u = 2^-53, the products neither underflow (a
+// nonzero product is >= 2^-298) nor overflow, so t1 = fl(a1 a2) and
+// t2 = fl(b1 b2) are each within (3u + 4u^2)|t| of the exact product, and
+// the final subtraction adds at most u(|t1| + |t2|). Hence
+//   |fl(t1 - t2) - orient| <= (4u + 4u^2)(|t1| + |t2|),
+// and the constant below (4u scaled by 1 + 2^-10) also covers the rounding of
+// the bound's own evaluation. |D| > bound certifies sign(D), and
+// [D - bound, D + bound] encloses the exact orientation.
+constexpr double kD64Rel = 4.4453e-16;  // 4 * 2^-53 * (1 + 2^-10) = 4.445229e-16, rounded up
+
+__device__ __forceinline__ double orient64(float ox, float oy, float ex, float ey, float px, float py, double& bound)
+{
+    const double a1 = (double)ex - (double)ox, a2 = (double)py - (double)oy;
+    const double b1 = (double)ey - (double)oy, b2 = (double)px - (double)ox;
+    const double t1 = a1 * a2, t2 = b1 * b2;
+    bound = kD64Rel * (fabs(t1) + fabs(t2));
+    return t1 - t2;
+}
+
+// sign of orient(o, e, p), exactly: float64 stage, then the 6-term expansion
 //   ex*py - ex*oy - ox*py - ey*px + ey*ox + oy*px
 __device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey, float px, float py)
 {
+    double bound;
+    const double d = orient64(ox, oy, ex, ey, px, py, bound);
+    if (d > bound) return 1;
+    if (-d > bound) return -1;
     double t[6];
     t[0] = (double)ex * (double)py;
     t[1] = -((double)ex * (double)oy);
@@ -175,11 +199,17 @@ __device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey,
 }
 
 // sign of area(P) - area(Q) for the edge o -> e, where area(X) = -orient(o,e,X):
+// float64 stage (areas with their bounds; fl(x) > fl(y) implies x > y), then
 //   (ex-ox)(qy-py) - (ey-oy)(qx-px)
 //   = ex*qy - ex*py - ox*qy + ox*py - ey*qx + ey*px + oy*qx - oy*px
 __device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float ey,
                                            float px, float py, float qx, float qy)
 {
+    double bp, bq;
+    const double ap = -orient64(ox, oy, ex, ey, px, py, bp);
+    const double aq = -orient64(ox, oy, ex, ey, qx, qy, bq);
+    if (ap - bp > aq + bq) return 1;
+    if (aq - bq > ap + bp) return -1;
     double t[8];
     t[0] = (double)ex * (double)qy;
     t[1] = -((double)ex * (double)py);

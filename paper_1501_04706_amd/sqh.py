@@ -57,11 +57,11 @@ class SqhStats(ctypes.Structure):
         ("hull_size", ctypes.c_int64),
         ("max_segments", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
+        ("ms_kernel", ctypes.c_double),
         ("ms_seed", ctypes.c_double),
         ("ms_split", ctypes.c_double),
         ("ms_first", ctypes.c_double),
         ("ms_pass", ctypes.c_double),
-        ("ms_table", ctypes.c_double),
         ("ms_emit", ctypes.c_double),
         ("pass_points", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
         ("pass_segments", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
@@ -106,6 +106,36 @@ def load() -> ctypes.CDLL:
     lib.sqh_get_trace.restype = c_int
     lib.sqh_strerror.argtypes = [c_int]
     lib.sqh_strerror.restype = ctypes.c_char_p
+    lib.sqh_autotune.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp, ctypes.c_size_t, vp, c_int]
+    lib.sqh_autotune.restype = c_int
+    lib.sqh_get_tuning.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.sqh_get_tuning.restype = c_int
+    lib.sqh_set_tuning.argtypes = [vp, ctypes.c_char_p]
+    lib.sqh_set_tuning.restype = c_int
+    lib.sqh_graph_create.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp, ctypes.c_size_t,
+                                     ctypes.POINTER(vp)]
+    lib.sqh_graph_create.restype = c_int
+    lib.sqh_graph_launch.argtypes = [vp, vp]
+    lib.sqh_graph_launch.restype = c_int
+    lib.sqh_graph_result.argtypes = [vp, ctypes.POINTER(i64), vp]
+    lib.sqh_graph_result.restype = c_int
+    lib.sqh_graph_destroy.argtypes = [vp]
+    lib.sqh_graph_destroy.restype = None
+    lib.sqh_engine_bytes.argtypes = [i64, i64, i64]
+    lib.sqh_engine_bytes.restype = ctypes.c_size_t
+    lib.sqh_engine_create.argtypes = [vp, vp, ctypes.c_size_t, i64, i64, i64, ctypes.POINTER(vp)]
+    lib.sqh_engine_create.restype = c_int
+    lib.sqh_engine_destroy.argtypes = [vp]
+    lib.sqh_engine_destroy.restype = None
+    lib.sqh_engine_admit.argtypes = [vp, vp, i64, ctypes.c_uint64, c_int, vp]
+    lib.sqh_engine_admit.restype = c_int
+    lib.sqh_engine_step.argtypes = [vp, c_int, vp]
+    lib.sqh_engine_step.restype = c_int
+    lib.sqh_engine_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), vp, i64, ctypes.POINTER(i64)]
+    lib.sqh_engine_poll.restype = c_int
+    lib.sqh_engine_status.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+    lib.sqh_engine_status.restype = c_int
     _lib = lib
     return lib
 
@@ -179,6 +209,97 @@ def sqh_strerror(code: int) -> str:
     return load().sqh_strerror(code).decode()
 
 
+def sqh_autotune(ctx: int, xy, set_off, n_sets: int, n_total: int, out, out_off, out_cap: int, ws,
+                 ws_bytes: int, stream=None, reps: int = 3) -> int:
+    return load().sqh_autotune(ctx, _ptr(xy), _ptr(set_off), n_sets, n_total, _ptr(out), _ptr(out_off),
+                               out_cap, _ptr(ws), ws_bytes, _stream_handle(stream), reps)
+
+
+def sqh_get_tuning(ctx: int) -> str:
+    lib = load()
+    need = lib.sqh_get_tuning(ctx, None, 0)
+    if need < 0:
+        raise SqhError(need, "sqh_get_tuning")
+    buf = ctypes.create_string_buffer(need)
+    lib.sqh_get_tuning(ctx, buf, need)
+    return buf.value.decode()
+
+
+def sqh_set_tuning(ctx: int, text: str) -> int:
+    return load().sqh_set_tuning(ctx, text.encode())
+
+
+def sqh_graph_create(ctx: int, xy, set_off, n_sets: int, n_total: int, out, out_off, out_cap: int, ws,
+                     ws_bytes: int):
+    """Returns (return code, graph handle)."""
+    g = ctypes.c_void_p()
+    rc = load().sqh_graph_create(ctx, _ptr(xy), _ptr(set_off), n_sets, n_total, _ptr(out), _ptr(out_off),
+                                 out_cap, _ptr(ws), ws_bytes, ctypes.byref(g))
+    return rc, g.value
+
+
+def sqh_graph_launch(graph: int, stream=None) -> int:
+    return load().sqh_graph_launch(graph, _stream_handle(stream))
+
+
+def sqh_graph_result(graph: int, stream=None):
+    """Returns (return code, total h)."""
+    h = ctypes.c_int64(0)
+    rc = load().sqh_graph_result(graph, ctypes.byref(h), _stream_handle(stream))
+    return rc, h.value
+
+
+def sqh_graph_destroy(graph: int) -> None:
+    load().sqh_graph_destroy(graph)
+
+
+def sqh_engine_bytes(slots: int, max_requests: int, stage_points: int) -> int:
+    return int(load().sqh_engine_bytes(slots, max_requests, stage_points))
+
+
+def sqh_engine_create(ctx: int, arena, arena_bytes: int, slots: int, max_requests: int, stage_points: int):
+    """Returns (return code, engine handle)."""
+    e = ctypes.c_void_p()
+    rc = load().sqh_engine_create(ctx, _ptr(arena), arena_bytes, slots, max_requests, stage_points,
+                                  ctypes.byref(e))
+    return rc, e.value
+
+
+def sqh_engine_destroy(engine: int) -> None:
+    load().sqh_engine_destroy(engine)
+
+
+def sqh_engine_admit(engine: int, xy, n: int, tag: int, stream=None) -> int:
+    """xy: a (n, 2) float32 numpy array (host) or torch tensor (device or host)."""
+    import numpy as np
+    if isinstance(xy, np.ndarray):
+        xy = np.ascontiguousarray(xy, dtype=np.float32)
+        return load().sqh_engine_admit(engine, xy.ctypes.data if n > 0 else None, n, tag, 0,
+                                       _stream_handle(stream))
+    on_dev = 1 if xy.is_cuda else 0
+    return load().sqh_engine_admit(engine, _ptr(xy) if n > 0 else None, n, tag, on_dev, _stream_handle(stream))
+
+
+def sqh_engine_step(engine: int, max_passes: int, stream=None) -> int:
+    return load().sqh_engine_step(engine, max_passes, _stream_handle(stream))
+
+
+def sqh_engine_poll(engine: int, h_out, cap: int):
+    """h_out: host int32 numpy array of cap entries. Returns (rc, tag, h)."""
+    tag = ctypes.c_uint64(0)
+    h = ctypes.c_int64(0)
+    rc = load().sqh_engine_poll(engine, ctypes.byref(tag), h_out.ctypes.data if cap > 0 else None, cap,
+                                ctypes.byref(h))
+    return rc, tag.value, h.value
+
+
+def sqh_engine_status(engine: int):
+    """Returns (rc, resident, staged, finished, free_slots)."""
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    rc = load().sqh_engine_status(engine, *[ctypes.byref(x) for x in v])
+    return (rc,) + tuple(x.value for x in v)
+
+
 # ---- conveniences ----
 
 class Hull:
@@ -250,3 +371,147 @@ class Hull:
 
     def stats(self) -> dict:
         return sqh_get_stats(self.ctx)
+
+    def autotune(self, xy, set_off=None, reps: int = 3, stream=None):
+        """Time the candidate launch shapes on this problem and keep the best."""
+        torch = self.torch
+        xy = xy.contiguous()
+        n_total = xy.shape[0]
+        nsets = 1 if set_off is None else set_off.numel() - 1
+        ws = self.workspace(n_total, nsets)
+        out = torch.empty(max(n_total, 1), dtype=torch.int32, device=self.device)
+        out_off = None if set_off is None else torch.empty(nsets + 1, dtype=torch.int64, device=self.device)
+        rc = sqh_autotune(self.ctx, xy, set_off, nsets, n_total, out, out_off, out.numel(), ws, ws.numel(),
+                          stream, reps)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_autotune")
+        return sqh_get_tuning(self.ctx)
+
+    def tuning(self) -> str:
+        return sqh_get_tuning(self.ctx)
+
+    def set_tuning(self, text: str):
+        rc = sqh_set_tuning(self.ctx, text)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_set_tuning")
+
+    def engine(self, slots: int, max_requests: int = 4096, stage_points: int | None = None) -> "Engine":
+        return Engine(self, slots, max_requests, stage_points)
+
+    def graph(self, xy, set_off=None):
+        """A replayable HIP graph of one (batched) hull on fixed buffers."""
+        return HullGraph(self, xy, set_off)
+
+
+class Engine:
+    """Continuous-batching serving engine over a torch-allocated arena."""
+
+    def __init__(self, H: "Hull", slots: int, max_requests: int = 4096, stage_points: int | None = None):
+        import numpy as np
+        torch = H.torch
+        self.H = H
+        slots = (slots + 63) // 64 * 64
+        stage_points = stage_points or slots
+        need = sqh_engine_bytes(slots, max_requests, stage_points)
+        if need == 0:
+            raise SqhError(SQH_EINVAL, "sqh_engine_bytes")
+        self.arena = torch.empty(need, dtype=torch.uint8, device=H.device)
+        rc, self.e = sqh_engine_create(H.ctx, self.arena, need, slots, max_requests, stage_points)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_engine_create")
+        self.slots = slots
+        self.buf = np.empty(1 << 16, dtype=np.int32)
+
+    def admit(self, xy, tag: int, stream=None) -> bool:
+        """True if admitted, False if the engine has no room right now."""
+        n = int(xy.shape[0])
+        rc = sqh_engine_admit(self.e, xy, n, tag, stream)
+        if rc == SQH_EBUSY:
+            return False
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_engine_admit")
+        return True
+
+    def step(self, max_passes: int = 4, stream=None) -> int:
+        rc = sqh_engine_step(self.e, max_passes, stream)
+        if rc < 0:
+            raise SqhError(rc, "sqh_engine_step")
+        return rc
+
+    def poll(self):
+        """Next finished request as (tag, hull int32 array or None if its input
+        was invalid), or None if nothing is finished."""
+        import numpy as np
+        while True:
+            rc, tag, h = sqh_engine_poll(self.e, self.buf, self.buf.size)
+            if rc == SQH_ENOTFOUND:
+                return None
+            if rc == SQH_ECAPACITY:
+                self.buf = np.empty(max(h, 2 * self.buf.size), dtype=np.int32)
+                continue
+            if rc == SQH_EINVAL:
+                return tag, None
+            if rc != SQH_OK:
+                raise SqhError(rc, "sqh_engine_poll")
+            return tag, self.buf[:h].copy()
+
+    def status(self) -> dict:
+        rc, res, stg, fin, free = sqh_engine_status(self.e)
+        return {"ok": rc == SQH_OK, "resident": res, "staged": stg, "finished": fin, "free_slots": free}
+
+    def close(self):
+        if self.e:
+            sqh_engine_destroy(self.e)
+            self.e = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HullGraph:
+    """Owns the buffers of one captured batched hull; launch() replays it."""
+
+    def __init__(self, H: "Hull", xy, set_off=None):
+        torch = H.torch
+        self.H = H
+        self.xy = xy.contiguous()
+        self.n_total = self.xy.shape[0]
+        self.set_off = set_off
+        self.nsets = 1 if set_off is None else set_off.numel() - 1
+        need = sqh_workspace_bytes(self.n_total, self.nsets)
+        if need == 0:
+            raise SqhError(SQH_EINVAL, "sqh_workspace_bytes")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=H.device)  # own workspace
+        self.out = torch.empty(max(self.n_total, 1), dtype=torch.int32, device=H.device)
+        self.out_off = torch.empty(self.nsets + 1, dtype=torch.int64, device=H.device)
+        rc, self.g = sqh_graph_create(H.ctx, self.xy, set_off, self.nsets, self.n_total, self.out,
+                                      self.out_off if set_off is not None else None, self.out.numel(),
+                                      self.ws, self.ws.numel())
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_graph_create")
+
+    def launch(self, stream=None):
+        rc = sqh_graph_launch(self.g, stream)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_graph_launch")
+
+    def result(self, stream=None):
+        """Synchronise; returns (out[:h], out_off or None)."""
+        rc, h = sqh_graph_result(self.g, stream)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_graph_result")
+        return self.out[:h], (self.out_off if self.set_off is not None else None)
+
+    def close(self):
+        if self.g:
+            sqh_graph_destroy(self.g)
+            self.g = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -155,7 +155,7 @@ int sqh_hull_batched(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, 
  * repetitions (1..100), and stores the fastest shape in the context for
  * this problem's size class, floor(log2(n_total)). Candidates: the number of
  * workgroups of the persistent kernel (all co-resident ones, 3/4, 1/2, 1/4)
- * times the tail threshold (2^14, 2^16, 2^18 points) below which one
+ * times the tail threshold (0, 2^13, 2^16 points; at most 256 segments) below which one
  * workgroup finishes the remaining passes. Later calls of any size use the
  * entry of the nearest class. The output of every shape is identical; only
  * time differs. Leaves the last candidate's result in d_out. Returns as
@@ -231,14 +231,15 @@ void sqh_graph_destroy(sqh_graph *graph);
  *   - emits the hulls of the requests left without segments (same result
  *     convention as sqh_hull, indices local to the request) and frees their
  *     slots.
- * An engine is used by one host thread; its calls are stream-ordered on the
- * stream passed, and sqh_engine_step synchronises that stream.
+ * An engine is used by one host thread. Admissions may use their own stream
+ * (a copy stream) and overlap a launched step.
  */
 typedef struct sqh_engine sqh_engine;
 
 /* Arena bytes for `slots` (a multiple of 64, 64 <= slots <= 2^31 - 128)
- * point slots, up to max_requests (1 .. 2^20) requests in flight and a
- * staging area of stage_points (1 .. slots) points. 0 if out of range. */
+ * point slots, up to max_requests (1 .. 2^20) requests in flight and two
+ * staging halves of stage_points (1 .. slots) points each (admissions fill
+ * one half while a launched step reads the other). 0 if out of range. */
 size_t sqh_engine_bytes(int64_t slots, int64_t max_requests, int64_t stage_points);
 
 /* Create an engine over device arena d_arena of arena_bytes bytes
@@ -265,11 +266,26 @@ int sqh_engine_admit(sqh_engine *engine, const float *xy, int64_t n, uint64_t ta
                      void *stream);
 
 /*
- * One step (see above) with at most max_passes (1 .. 65536) passes.
- * Returns the number of requests that finished in this step (their hulls
- * are then waiting for sqh_engine_poll), or SQH_EINVAL / SQH_EDEVICE (the
- * engine is unusable after SQH_EDEVICE). Synchronises the stream.
+ * Enqueue one step (see above) with at most max_passes (1 .. 65536) passes
+ * on `stream` and return without waiting. The step takes every request
+ * admitted so far (it waits on the device for their copies, whatever stream
+ * they were admitted on); requests admitted while it runs go to the other
+ * staging half and join the next step. Returns SQH_OK; SQH_ENOTFOUND if no
+ * request is staged or resident; SQH_EBUSY if a step is already in flight;
+ * SQH_EINVAL; SQH_EDEVICE.
  */
+int sqh_engine_launch(sqh_engine *engine, int max_passes, void *stream);
+
+/*
+ * Wait for the launched step and collect it: returns the number of requests
+ * that finished in it (their hulls then wait for sqh_engine_poll; their
+ * slots are free again), 0 if no step is in flight, or SQH_EDEVICE (the
+ * engine is unusable afterwards).
+ */
+int sqh_engine_finish(sqh_engine *engine);
+
+/* sqh_engine_launch followed by sqh_engine_finish (0 if there is nothing to
+ * do). */
 int sqh_engine_step(sqh_engine *engine, int max_passes, void *stream);
 
 /*

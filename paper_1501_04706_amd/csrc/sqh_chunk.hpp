@@ -351,6 +351,18 @@ __device__ __forceinline__ void process_wave(const Pol& pol, int wb, int we, int
     // group g ended at ge: finalise it, or hand it to the block if it started
     // before this part; then move to the next group (if inside the part)
     auto end_group = [&](void) {
+        // the next group holding position ge: with non-empty groups its loads
+        // are issued before this group's reduction and finalisation
+        const bool more = ge < we;
+        int g2 = g, ge2 = ge;
+        Ctx c2 = c;
+        if constexpr (Pol::MIDDLE) {
+            if (more) {
+                g2 = g + 1;
+                ge2 = pol.group_end(g2);
+                c2 = pol.ctx(g2);
+            }
+        }
         if constexpr (AGG) {
             Agg<NB> tot;
 #pragma unroll
@@ -367,13 +379,20 @@ __device__ __forceinline__ void process_wave(const Pol& pol, int wb, int we, int
                 }
             }
         }
-        if (ge < we) {
-            // the next group holding position ge (skipping empty ones)
-            const int q = ge;
-            ++g;
-            ge = pol.group_end(g);
-            while (ge <= q) ge = pol.group_end(++g);
-            c = pol.ctx(g);
+        if constexpr (!Pol::MIDDLE) {
+            if (more) {
+                // skipping empty groups
+                const int q0 = ge;
+                g2 = g + 1;
+                ge2 = pol.group_end(g2);
+                while (ge2 <= q0) ge2 = pol.group_end(++g2);
+                c2 = pol.ctx(g2);
+            }
+        }
+        if (more) {
+            g = g2;
+            ge = ge2;
+            c = c2;
         } else {
             open = false;
         }
@@ -465,57 +484,78 @@ __device__ __forceinline__ void process_chunk(const Pol& pol, int cb, int ce, in
         }
         if (wb < we) process_wave<Pol, MODE>(pol, wb, we, glo, ghi, nullptr, sh, ctr);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            // chain the waves: prefix of each wave's first group, closed groups
-            int run_g = -1;
-            Agg<NB> run;
-            agg_clear(run);
-            for (int v = 0; v < kWaves; ++v) {
-                if (sh.wempty[v]) continue;
-                int vb, ve;
-                wave_part(cb, ce, v, vb, ve);
-                const int g0 = sh.wfirst_g[v];
-                Agg<NB> pre;
-                agg_clear(pre);
-                if (g0 == run_g) pre = run;
+        if (w == 0) {
+            // Chain the parts, one lane per wave (active waves are a prefix).
+            // R[v], the aggregate of the group running out of part v, is a
+            // segmented inclusive scan: R[v] = R[v-1] (+) wlast[v] when part v
+            // lies inside the group running into it, else wlast[v]. The count
+            // prefix of part v's first group is R[v-1].
+            const int v = lane;
+            const bool act = v < kWaves && !sh.wempty[v];
+            int g0 = -1, lg = -1;
+            bool fb = false, fd = false;
+            if (act) {
+                g0 = sh.wfirst_g[v];
+                fb = sh.wfirst_before[v] != 0;
+                fd = sh.wfirst_done[v] != 0;
+                lg = sh.wlast_g[v];
+            }
+            const bool cont = act && v > 0 && fb && !fd && lg == g0;
+            const bool use_pre = act && fb && v > 0;
+            const int last_act = 63 - __clzll(__ballot(act));
+            {
+                const Ctx cs = pol.ctx(act && lg >= 0 ? lg : glo);
 #pragma unroll
-                for (int k = 0; k < NB; ++k) sh.wpref[v][k] = pre.cnt[k];
-                if (sh.wfirst_done[v]) {
-                    const Ctx c = pol.ctx(g0);
-                    Agg<NB> tot = pre;
-                    agg_add<Pol, true>(pol, c, tot, sh.wfirst_total[v], ctr);
-                    if (pol.group_start(g0) >= cb) {
-                        pol.finalize(c, g0, tot);
-                    } else {
-                        sh.first_total = tot;
-                        sh.first_done = 1;
+                for (int k = 0; k < NB; ++k) {
+                    int cnt = 0;
+                    Cand best = no_cand();
+                    if (act && lg >= 0) {
+                        cnt = Pol::COUNTS ? sh.wlast[v].cnt[k] : 0;
+                        best = sh.wlast[v].best[k];
                     }
-                    run_g = sh.wlast_g[v];
-                    run = sh.wlast[v];
-                } else if (sh.wfirst_before[v] && sh.wlast_g[v] == g0) {
-                    const Ctx c = pol.ctx(g0);
-                    agg_add<Pol, true>(pol, c, pre, sh.wlast[v], ctr);
-                    run = pre;
-                    run_g = g0;
-                } else {
-                    run_g = sh.wlast_g[v];
-                    run = sh.wlast[v];
-                }
-                if (run_g >= 0 && pol.group_end(run_g) <= ve) {  // (not reached: parts close such groups)
-                    // the running group ends exactly at this part's end
-                    const Ctx c = pol.ctx(run_g);
-                    if (pol.group_start(run_g) >= cb) {
-                        pol.finalize(c, run_g, run);
-                    } else {
-                        sh.first_total = run;
-                        sh.first_done = 1;
+                    bool flag = !cont;
+#pragma unroll
+                    for (int d = 1; d < kWaves; d <<= 1) {
+                        const int oc = __shfl_up(cnt, d);
+                        const Cand ob = shfl_up_cand(best, d);
+                        const int of = __shfl_up(flag ? 1 : 0, d);
+                        if (v >= d && !flag) {
+                            cnt += oc;
+                            if (pol.beats(cs, k, ob, best, ctr)) best = ob;
+                            flag = of != 0;
+                        }
                     }
-                    run_g = -1;
-                    agg_clear(run);
+                    const int pc = __shfl_up(cnt, 1);
+                    const Cand pb_ = shfl_up_cand(best, 1);
+                    if (act) {
+                        sh.wpref[v][k] = use_pre ? pc : 0;
+                        sh.red[v].cnt[k] = use_pre ? pc : 0;
+                        sh.red[v].best[k] = use_pre ? pb_ : no_cand();
+                    }
+                    if (v == last_act) {
+                        sh.carry.cnt[k] = lg >= 0 ? cnt : 0;
+                        sh.carry.best[k] = lg >= 0 ? best : no_cand();
+                    }
                 }
             }
-            sh.carry_g = run_g;
-            sh.carry = run;
+            if (v == last_act) sh.carry_g = lg;
+            if (fd) {
+                // part v closes its first group: prefix (+) its own aggregate
+                const Ctx cf = pol.ctx(g0);
+                Agg<NB> tot;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    tot.cnt[k] = sh.red[v].cnt[k] + sh.wfirst_total[v].cnt[k];
+                    tot.best[k] = sh.wfirst_total[v].best[k];
+                    if (pol.beats(cf, k, sh.red[v].best[k], tot.best[k], ctr)) tot.best[k] = sh.red[v].best[k];
+                }
+                if (pol.group_start(g0) >= cb) {
+                    pol.finalize(cf, g0, tot);
+                } else {
+                    sh.first_total = tot;
+                    sh.first_done = 1;
+                }
+            }
         }
         __syncthreads();
     } else {

@@ -63,13 +63,13 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(HullArgs a)
         }
         stamp(a, 1);
         {
-            PolSplit pol{a.xy, a.gstart, a.sbase, a.bad, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, a.G};
+            PolSplit pol{a.xy, a.gstart, a.sbase, a.bad, a.sets, a.bitmap, a.vidx, nullptr, a.info, a.fp64, a.G};
             phase_reduce(a, pol, a.N, shP, red, ctr);
         }
         stamp(a, 2);
         {
             PolFirst pol{a.xy,      a.gstart, a.sbase, a.bad,   a.sets, a.X[cur], a.Y[cur], a.I[cur], a.recs,
-                         a.rec_cid, a.bitmap, a.vidx,  a.vlist, a.info, a.fp64,   a.G};
+                         a.rec_cid, a.bitmap, a.vidx,  nullptr, a.info, a.fp64,   a.G};
             phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[cur], a.seg_cid[cur], a.vstart[cur],
                                            a.sv + 2 * cur, res, shF, red, ctr);
         }
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(HullArgs a)
         const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
         if (b == 0) note_pass(a, pass, S, V);
         if (S <= 0 || pass >= a.max_passes) break;
-        if (V <= a.tail_points) {
+        if (V <= a.tail_points && S <= kTailSegs) {
             if (b == 0) {
                 for (int p = pass;; ++p) {
                     const int S2 = ld_flag(a.sv + 2 * cur), V2 = ld_flag(a.sv + 2 * cur + 1);

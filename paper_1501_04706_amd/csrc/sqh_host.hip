@@ -214,6 +214,8 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
     return SQH_OK;
 }
 
+void phase_times(const HullInfo& hi, sqh_stats& S);
+
 // Read the status words back (synchronising the stream), fill the context's
 // counters and map the device status to a return code.
 int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t* h_total, hipStream_t st,
@@ -245,22 +247,7 @@ int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t
         S.orient_exact += ctx->hstats[4 * i + 1];
         S.cmp_exact += ctx->hstats[4 * i + 2];
     }
-    // device timestamps (100 MHz constant clock) at phase ends, workgroup 0
-    if (hi.nstamps > 1) {
-        const double tick_ms = 1e-5;
-        auto dt = [&](int i) { return (double)(hi.stamp[i] - hi.stamp[i - 1]) * tick_ms; };
-        for (int i = 1; i < hi.nstamps && i < kMaxStamps; ++i) {
-            const int tag = hi.stamp_tag[i];
-            if (tag == 1) S.ms_seed += dt(i);
-            else if (tag == 2) S.ms_split += dt(i);
-            else if (tag == 3) S.ms_first += dt(i);
-            else if (tag == 4) S.ms_emit += dt(i);
-            else if (tag >= 100) {
-                S.ms_pass += dt(i);
-                if (tag - 100 < SQH_MAX_TIMED_PASSES) S.pass_ms[tag - 100] = dt(i);
-            }
-        }
-    }
+    phase_times(hi, S);
     const int64_t h = hi.h_total;
     S.hull_size = h;
     if (timed) {
@@ -272,6 +259,26 @@ int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t
     if (e & (kErrNonFinite | kErrBounds)) return SQH_EINVAL;
     if (e) return SQH_EDEVICE;
     return h > out_cap ? SQH_ECAPACITY : SQH_OK;
+}
+
+// Device timestamps (100 MHz constant clock) taken by workgroup 0 at phase
+// ends, as phase durations.
+void phase_times(const HullInfo& hi, sqh_stats& S)
+{
+    if (hi.nstamps <= 1) return;
+    const double tick_ms = 1e-5;
+    auto dt = [&](int i) { return (double)(hi.stamp[i] - hi.stamp[i - 1]) * tick_ms; };
+    for (int i = 1; i < hi.nstamps && i < kMaxStamps; ++i) {
+        const int tag = hi.stamp_tag[i];
+        if (tag == 1) S.ms_seed += dt(i);
+        else if (tag == 2) S.ms_split += dt(i);
+        else if (tag == 3) S.ms_first += dt(i);
+        else if (tag == 4) S.ms_emit += dt(i);
+        else if (tag >= 100) {
+            S.ms_pass += dt(i);
+            if (tag - 100 < SQH_MAX_TIMED_PASSES) S.pass_ms[tag - 100] = dt(i);
+        }
+    }
 }
 
 int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64_t* d_set_off, int32_t* d_out,
@@ -322,7 +329,8 @@ bool read_int_key(const char* obj, const char* end, const char* key, long& v)
 namespace {
 
 // Device arena of a serving engine with K slots (multiple of 64), R request
-// entries and a staging area of SC points.
+// entries and two staging halves of SC points (admissions fill one half while
+// a step reads the other).
 struct EngLayout {
     int64_t K, R, SC, scap, rcap;
     size_t x[2], y[2], id[2], segs[2], seg_cid[2], vstart[2];
@@ -365,7 +373,7 @@ bool make_eng_layout(int64_t K, int64_t R, int64_t SC, EngLayout& L)
     L.res_n = take(sizeof(int) * (size_t)R);
     L.res_alive = take(sizeof(int) * (size_t)R);
     L.res_h = take(sizeof(int) * (size_t)R);
-    L.stage = take(sizeof(float2) * (size_t)SC);
+    L.stage = take(sizeof(float2) * (size_t)(2 * SC));  // two halves: one per step in flight
     L.vlist = take(sizeof(int2));
     L.slots = take(sizeof(ChunkSlot<4>) * (size_t)kMaxGrid);
     L.ctab = take(sizeof(Pair) * (size_t)kMaxGrid);
@@ -395,10 +403,16 @@ struct sqh_engine {
     sqh_ctx* ctx = nullptr;
     char* arena = nullptr;
     EngLayout L{};
-    int cur = 0;
+    int cur = 0;    // survivor buffer holding the resident segments
+    int side = 0;   // staging half that admissions fill
     bool broken = false;
+    bool inflight = false;
+    bool admitted = false;  // admissions since the last launch (ev_admit is recorded)
     std::map<int64_t, int64_t> free_ranges;  // first slot -> length (64-aligned)
-    std::vector<EngReq> staged, resident;
+    std::vector<EngReq> staged;     // admitted, waiting for the next launch
+    std::vector<EngReq> resident;   // segments in the table
+    std::vector<EngReq> step_all;   // launched step: all requests, by first slot
+    std::vector<EngReq> step_new;   // launched step: its new requests
     int64_t stage_used = 0;
     std::deque<EngDone> done;
     int* h_up = nullptr;     // pinned: gstart (R+1), sbase (R), res_base (R), res_n (R)
@@ -406,10 +420,19 @@ struct sqh_engine {
     int32_t* h_bounce = nullptr;
     int64_t bounce_cap = 0;
     HullInfo* h_info = nullptr;
+    hipEvent_t ev_admit = nullptr, ev_done = nullptr;
+    hipStream_t step_stream = nullptr;
     int64_t steps = 0;
 };
 
 namespace {
+
+int64_t up_points(const sqh_engine* e)
+{
+    int64_t n = 0;
+    for (const auto& q : e->step_new) n += q.n;
+    return n;
+}
 
 bool eng_alloc(sqh_engine* e, int64_t n, int64_t& base)
 {
@@ -540,7 +563,7 @@ int sqh_autotune(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, int64_
     const int cls = log2_class(n_total);
     const int m = c->max_grid;
     const int grids[4] = {m, std::max(1, (3 * m) / 4), std::max(1, m / 2), std::max(1, m / 4)};
-    const int tails[3] = {1 << 14, 1 << 16, 1 << 18};
+    const int tails[3] = {0, 1 << 13, 1 << 16};
     TuneEntry best{cls, m, kTailPoints};
     double best_ms = 1e300;
     int64_t h = 0;
@@ -723,7 +746,9 @@ int sqh_engine_create(sqh_ctx* c, void* d_arena, size_t arena_bytes, int64_t slo
         hipHostMalloc(reinterpret_cast<void**>(&e->h_down), down, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&e->h_bounce), sizeof(int32_t) * (size_t)e->bounce_cap,
                       hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&e->h_info), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&e->h_info), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_admit, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_done, hipEventDisableTiming) != hipSuccess) {
         sqh_engine_destroy(e);
         return SQH_EDEVICE;
     }
@@ -741,10 +766,13 @@ int sqh_engine_create(sqh_ctx* c, void* d_arena, size_t arena_bytes, int64_t slo
 void sqh_engine_destroy(sqh_engine* e)
 {
     if (!e) return;
+    if (e->inflight && e->ev_done) (void)hipEventSynchronize(e->ev_done);
     if (e->h_up) (void)hipHostFree(e->h_up);
     if (e->h_down) (void)hipHostFree(e->h_down);
     if (e->h_bounce) (void)hipHostFree(e->h_bounce);
     if (e->h_info) (void)hipHostFree(e->h_info);
+    if (e->ev_admit) (void)hipEventDestroy(e->ev_admit);
+    if (e->ev_done) (void)hipEventDestroy(e->ev_done);
     delete e;
 }
 
@@ -757,28 +785,32 @@ int sqh_engine_admit(sqh_engine* e, const float* xy, int64_t n, uint64_t tag, in
         e->done.push_back(EngDone{tag, SQH_OK, {}});
         return SQH_OK;
     }
-    if ((int64_t)(e->staged.size() + e->resident.size()) >= e->L.R) return SQH_EBUSY;
+    const size_t in_flight = e->inflight ? e->step_all.size() : e->resident.size();
+    if ((int64_t)(e->staged.size() + in_flight) >= e->L.R) return SQH_EBUSY;
     if (e->stage_used + n > e->L.SC) return SQH_EBUSY;
     int64_t base = 0;
     if (!eng_alloc(e, n, base)) return SQH_EBUSY;
     HIP_OK(hipSetDevice(e->ctx->device));
-    float2* stage = reinterpret_cast<float2*>(e->arena + e->L.stage) + e->stage_used;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float2* stage = reinterpret_cast<float2*>(e->arena + e->L.stage) + (size_t)e->side * e->L.SC + e->stage_used;
     if (hipMemcpyAsync(stage, xy, sizeof(float2) * (size_t)n,
-                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                       static_cast<hipStream_t>(stream)) != hipSuccess) {
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(e->ev_admit, st) != hipSuccess) {
         eng_free(e, base, (n + 63) & ~63LL);
         return SQH_EDEVICE;
     }
+    e->admitted = true;
     e->staged.push_back(EngReq{tag, base, n, (n + 63) & ~63LL, e->stage_used});
     e->stage_used += n;
     return SQH_OK;
 }
 
-int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
+int sqh_engine_launch(sqh_engine* e, int max_passes, void* stream)
 {
     if (!e || max_passes < 1 || max_passes > kMaxPasses) return SQH_EINVAL;
     if (e->broken) return SQH_EDEVICE;
-    if (e->staged.empty() && e->resident.empty()) return 0;
+    if (e->inflight) return SQH_EBUSY;
+    if (e->staged.empty() && e->resident.empty()) return SQH_ENOTFOUND;
     sqh_ctx* c = e->ctx;
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_OK(hipSetDevice(c->device));
@@ -786,25 +818,30 @@ int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
     const int64_t R = L.R;
     const int G = (int)e->staged.size();
     // all requests in slot order (new ones included) for the census
-    std::vector<EngReq> all(e->resident);
-    all.insert(all.end(), e->staged.begin(), e->staged.end());
-    std::sort(all.begin(), all.end(), [](const EngReq& p, const EngReq& q) { return p.base < q.base; });
-    const int nres = (int)all.size();
+    e->step_all = e->resident;
+    e->step_all.insert(e->step_all.end(), e->staged.begin(), e->staged.end());
+    std::sort(e->step_all.begin(), e->step_all.end(),
+              [](const EngReq& p, const EngReq& q) { return p.base < q.base; });
+    e->step_new.swap(e->staged);
+    e->staged.clear();
+    const int nres = (int)e->step_all.size();
     int* up_gstart = e->h_up;
     int* up_sbase = e->h_up + (R + 1);
     int* up_rbase = e->h_up + (2 * R + 1);
     int* up_rn = e->h_up + (3 * R + 1);
     for (int g = 0; g < G; ++g) {
-        up_gstart[g] = (int)e->staged[g].stage_at;
-        up_sbase[g] = (int)e->staged[g].base;
+        up_gstart[g] = (int)e->step_new[g].stage_at;
+        up_sbase[g] = (int)e->step_new[g].base;
     }
     up_gstart[G] = (int)e->stage_used;
     for (int r = 0; r < nres; ++r) {
-        up_rbase[r] = (int)all[r].base;
-        up_rn[r] = (int)all[r].n;
+        up_rbase[r] = (int)e->step_all[r].base;
+        up_rn[r] = (int)e->step_all[r].n;
     }
     char* A = e->arena;
     auto at = [&](size_t off) { return static_cast<void*>(A + off); };
+    if (e->admitted) HIP_OK(hipStreamWaitEvent(st, e->ev_admit, 0));  // staged points have arrived
+    e->admitted = false;
     HIP_OK(hipMemcpyAsync(at(L.gstart), up_gstart, sizeof(int) * (size_t)(G + 1), hipMemcpyHostToDevice, st));
     if (G > 0) HIP_OK(hipMemcpyAsync(at(L.sbase), up_sbase, sizeof(int) * (size_t)G, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(at(L.res_base), up_rbase, sizeof(int) * (size_t)nres, hipMemcpyHostToDevice, st));
@@ -812,7 +849,7 @@ int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
 
     const TuneEntry tu = pick_tuning(c, e->stage_used > 0 ? e->stage_used : 1);
     HullArgs a{};
-    a.xy = static_cast<const float2*>(at(L.stage));
+    a.xy = reinterpret_cast<const float2*>(A + L.stage) + (size_t)e->side * L.SC;
     a.N = (int)e->stage_used;
     a.G = G;
     for (int b = 0; b < 2; ++b) {
@@ -870,7 +907,34 @@ int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
     HIP_OK(hipMemcpyAsync(dn_err, at(L.err), sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(e->h_info, at(L.info), offsetof(HullInfo, trace), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(c->hstats, at(L.stats), sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipEventRecord(e->ev_done, st));
+    // later admissions fill the other staging half
+    e->side ^= 1;
+    e->stage_used = 0;
+    e->step_stream = st;
+    e->inflight = true;
+    return SQH_OK;
+}
+
+int sqh_engine_finish(sqh_engine* e)
+{
+    if (!e) return SQH_EINVAL;
+    if (e->broken) return SQH_EDEVICE;
+    if (!e->inflight) return 0;
+    sqh_ctx* c = e->ctx;
+    hipStream_t st = e->step_stream;
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(hipEventSynchronize(e->ev_done));
+    e->inflight = false;
+    const EngLayout& L = e->L;
+    const int64_t R = L.R;
+    char* A = e->arena;
+    const int G = (int)e->step_new.size();
+    const int nres = (int)e->step_all.size();
+    int* dn_alive = e->h_down;
+    int* dn_h = e->h_down + R;
+    int* dn_bad = e->h_down + 2 * R;
+    int* dn_err = e->h_down + 3 * R;
     if (*dn_err & (kErrSpin | kErrBounds)) {
         e->broken = true;
         return SQH_EDEVICE;
@@ -880,8 +944,9 @@ int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
     {
         sqh_stats& S = c->stats;
         S = sqh_stats{};
-        S.points = e->stage_used;
+        S.points = up_points(e);
         S.passes = e->h_info->passes;
+        phase_times(*e->h_info, S);
         for (int i = 0; i < kStatSlots; ++i) {
             S.orient_evals += c->hstats[4 * i + 0];
             S.orient_exact += c->hstats[4 * i + 1];
@@ -894,59 +959,66 @@ int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
     // bad inputs among the new requests (their sets were skipped)
     std::map<int64_t, int> bad_base;
     for (int g = 0; g < G; ++g)
-        if (dn_bad[g]) bad_base[e->staged[g].base] = 1;
+        if (dn_bad[g]) bad_base[e->step_new[g].base] = 1;
     // collect finished requests: copy their hulls through the pinned bounce buffer
     int finished = 0;
     std::vector<EngReq> keep;
     std::vector<std::pair<EngReq, int>> fin;
     for (int r = 0; r < nres; ++r) {
-        if (dn_alive[r]) keep.push_back(all[r]);
-        else fin.push_back({all[r], dn_h[r]});
+        if (dn_alive[r]) keep.push_back(e->step_all[r]);
+        else fin.push_back({e->step_all[r], dn_h[r]});
     }
+    auto deliver = [&](const EngReq& q, const int32_t* h, int64_t cnt) {
+        EngDone d{q.tag, SQH_OK, std::vector<int32_t>(h, h + cnt)};
+        if (bad_base.count(q.base)) {
+            d.status = SQH_EINVAL;
+            d.hull.clear();
+        }
+        e->done.push_back(std::move(d));
+        eng_free(e, q.base, q.alloc);
+        ++finished;
+    };
     size_t i0 = 0;
     while (i0 < fin.size()) {
+        if (fin[i0].second > e->bounce_cap) {
+            // one hull larger than the bounce buffer: copy it directly
+            std::vector<int32_t> tmp((size_t)fin[i0].second);
+            HIP_OK(hipMemcpy(tmp.data(), A + L.hout + sizeof(int) * (size_t)fin[i0].first.base,
+                             sizeof(int) * tmp.size(), hipMemcpyDeviceToHost));
+            deliver(fin[i0].first, tmp.data(), (int64_t)tmp.size());
+            ++i0;
+            continue;
+        }
         int64_t used = 0;
         size_t i1 = i0;
-        while (i1 < fin.size() && (i1 == i0 || used + fin[i1].second <= e->bounce_cap)) {
+        while (i1 < fin.size() && used + fin[i1].second <= e->bounce_cap) {
             const int h = fin[i1].second;
-            if (h > e->bounce_cap) break;  // (cannot happen: h <= n <= stage capacity... checked below)
             if (h > 0)
                 HIP_OK(hipMemcpyAsync(e->h_bounce + used, A + L.hout + sizeof(int) * (size_t)fin[i1].first.base,
                                       sizeof(int) * (size_t)h, hipMemcpyDeviceToHost, st));
             used += h;
             ++i1;
         }
-        if (i1 == i0) {
-            // one hull larger than the bounce buffer: copy it directly
-            const EngReq& q = fin[i0].first;
-            EngDone d{q.tag, SQH_OK, std::vector<int32_t>((size_t)fin[i0].second)};
-            HIP_OK(hipMemcpy(d.hull.data(), A + L.hout + sizeof(int) * (size_t)q.base,
-                             sizeof(int) * (size_t)fin[i0].second, hipMemcpyDeviceToHost));
-            if (bad_base.count(q.base)) { d.status = SQH_EINVAL; d.hull.clear(); }
-            e->done.push_back(std::move(d));
-            eng_free(e, q.base, q.alloc);
-            ++finished;
-            ++i0;
-            continue;
-        }
         HIP_OK(hipStreamSynchronize(st));
         int64_t off = 0;
         for (size_t i = i0; i < i1; ++i) {
-            const EngReq& q = fin[i].first;
-            const int h = fin[i].second;
-            EngDone d{q.tag, SQH_OK, std::vector<int32_t>(e->h_bounce + off, e->h_bounce + off + h)};
-            if (bad_base.count(q.base)) { d.status = SQH_EINVAL; d.hull.clear(); }
-            e->done.push_back(std::move(d));
-            off += h;
-            eng_free(e, q.base, q.alloc);
-            ++finished;
+            deliver(fin[i].first, e->h_bounce + off, fin[i].second);
+            off += fin[i].second;
         }
         i0 = i1;
     }
     e->resident.swap(keep);
-    e->staged.clear();
-    e->stage_used = 0;
+    e->step_new.clear();
+    e->step_all.clear();
     return finished;
+}
+
+int sqh_engine_step(sqh_engine* e, int max_passes, void* stream)
+{
+    const int rc = sqh_engine_launch(e, max_passes, stream);
+    if (rc == SQH_ENOTFOUND) return 0;  // nothing resident or staged
+    if (rc != SQH_OK) return rc;
+    return sqh_engine_finish(e);
 }
 
 int sqh_engine_poll(sqh_engine* e, uint64_t* tag, int32_t* h_out, int64_t cap, int64_t* h)
@@ -971,7 +1043,7 @@ int sqh_engine_status(const sqh_engine* e, int64_t* resident, int64_t* staged, i
                       int64_t* free_slots)
 {
     if (!e) return SQH_EINVAL;
-    if (resident) *resident = (int64_t)e->resident.size();
+    if (resident) *resident = (int64_t)(e->inflight ? e->step_all.size() : e->resident.size());
     if (staged) *staged = (int64_t)e->staged.size();
     if (finished) *finished = (int64_t)e->done.size();
     if (free_slots) {

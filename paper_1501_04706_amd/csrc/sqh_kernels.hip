@@ -41,12 +41,13 @@ __device__ __forceinline__ int search_le(const int* start, int q, int lo, int hi
 // vertices by key.
 struct HullInfo;
 __device__ void note_vertex(HullInfo* info, int2* vlist, int key, int id);
+// vlist == nullptr: no vertex list (the emission ranks the bitmap)
 __device__ __forceinline__ void record_vertex(uint64_t* bitmap, int* vidx, int2* vlist, HullInfo* info, int key,
                                               int id)
 {
     atomicOr((unsigned long long*)&bitmap[key >> 6], 1ull << (key & 63));
     gst(vidx + key, id);
-    note_vertex(info, vlist, key, id);
+    if (vlist) note_vertex(info, vlist, key, id);
 }
 
 // ============================================================ k_seed ==
@@ -116,8 +117,10 @@ struct PolSplit {
     static constexpr bool COUNTS = true, SCATTER = false, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
     struct Ctx {
-        Edge ab, ba;
+        float ax, ay, bx, by;   // A->B and B->A are rebuilt where used
         int base, sbase, skip;  // first read position, first slot (vertex keys)
+        __device__ __forceinline__ Edge ab() const { return make_edge(ax, ay, bx, by); }
+        __device__ __forceinline__ Edge ba() const { return make_edge(bx, by, ax, ay); }
     };
     const float2* xy;
     const int* gstart;
@@ -139,8 +142,7 @@ struct PolSplit {
     {
         const SetInfo s = gld(sets + g);
         Ctx c;
-        c.ab = make_edge(s.ax, s.ay, s.bx, s.by);
-        c.ba = make_edge(s.bx, s.by, s.ax, s.ay);
+        c.ax = s.ax; c.ay = s.ay; c.bx = s.bx; c.by = s.by;
         c.base = gld(gstart + g);
         c.sbase = gld(sbase + g);
         // lexmin and lexmax coincide only if every point sits at one position
@@ -159,9 +161,10 @@ struct PolSplit {
     {
         if (c.skip) return kNone;
         ++ctr.orient;
-        const Orient32 o = orient32(c.ab, x, y);
+        const Edge ab = c.ab();
+        const Orient32 o = orient32(ab, x, y);
         int sg = fast_sign(o, fp64 != 0);
-        settle(sg, sg == 0, c.ab, x, y, ctr.orient_exact);
+        settle(sg, sg == 0, ab, x, y, ctr.orient_exact);
         k.a = sg < 0 ? -o.d : o.d;
         k.w = 2.0f * o.es;
         k.x = x; k.y = y; k.id = id;
@@ -173,7 +176,7 @@ struct PolSplit {
     }
     __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
-        return sqh::beats(k == 0 ? c.ab : c.ba, P, Q, fp64 != 0, ctr.cmp_exact);
+        return sqh::beats(k == 0 ? c.ab() : c.ba(), P, Q, fp64 != 0, ctr.cmp_exact);
     }
     __device__ __forceinline__ int place(const Ctx&, int, int, int) const { return 0; }
     __device__ __forceinline__ void store(int, float, float, int) const {}
@@ -203,10 +206,21 @@ struct PolFirst {
     static constexpr int NB = 4;
     static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
+    // A, B, C_lo, C_up as loaded; the edges A->B, A->C_lo, C_lo->B, B->C_up
+    // and C_up->A are rebuilt where used
     struct Ctx {
-        Edge ab;
-        Edge e[4];  // A->C_lo, C_lo->B, B->C_up, C_up->A
+        float ax, ay, bx, by, lx, ly, ux, uy;
         int base, sbase, n_lo, n_up, skip;  // first read position, first slot
+        __device__ __forceinline__ Edge ab() const { return make_edge(ax, ay, bx, by); }
+        __device__ __forceinline__ Edge edge(int k) const
+        {
+            switch (k) {
+            case 0: return make_edge(ax, ay, lx, ly);
+            case 1: return make_edge(lx, ly, bx, by);
+            case 2: return make_edge(bx, by, ux, uy);
+            default: return make_edge(ux, uy, ax, ay);
+            }
+        }
     };
     const float2* xy;
     const int* gstart;
@@ -233,11 +247,8 @@ struct PolFirst {
     {
         const SetInfo s = gld(sets + g);
         Ctx c;
-        c.ab = make_edge(s.ax, s.ay, s.bx, s.by);
-        c.e[0] = make_edge(s.ax, s.ay, s.clx, s.cly);
-        c.e[1] = make_edge(s.clx, s.cly, s.bx, s.by);
-        c.e[2] = make_edge(s.bx, s.by, s.cux, s.cuy);
-        c.e[3] = make_edge(s.cux, s.cuy, s.ax, s.ay);
+        c.ax = s.ax; c.ay = s.ay; c.bx = s.bx; c.by = s.by;
+        c.lx = s.clx; c.ly = s.cly; c.ux = s.cux; c.uy = s.cuy;
         c.base = gld(gstart + g);
         c.sbase = gld(sbase + g);
         c.n_lo = s.n_lo;
@@ -259,12 +270,14 @@ struct PolFirst {
         if (c.skip) return kNone;
         const bool f64 = fp64 != 0;
         ctr.orient += 3;
-        const Orient32 o = orient32(c.ab, x, y);
+        const Edge ab = c.ab();
+        const Orient32 o = orient32(ab, x, y);
         int side = fast_sign(o, f64);
-        settle(side, side == 0, c.ab, x, y, ctr.orient_exact);
+        settle(side, side == 0, ab, x, y, ctr.orient_exact);
         const bool up = side > 0;
-        const Edge E1 = up ? c.e[2] : c.e[0];
-        const Edge E2 = up ? c.e[3] : c.e[1];
+        // lower side: A->C_lo, C_lo->B; upper side: B->C_up, C_up->A
+        const Edge E1 = up ? make_edge(c.bx, c.by, c.ux, c.uy) : make_edge(c.ax, c.ay, c.lx, c.ly);
+        const Edge E2 = up ? make_edge(c.ux, c.uy, c.ax, c.ay) : make_edge(c.lx, c.ly, c.bx, c.by);
         const Orient32 o1 = orient32(E1, x, y);
         const Orient32 o2 = orient32(E2, x, y);
         int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
@@ -281,7 +294,7 @@ struct PolFirst {
     }
     __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
-        return sqh::beats(c.e[k], P, Q, fp64 != 0, ctr.cmp_exact);
+        return sqh::beats(c.edge(k), P, Q, fp64 != 0, ctr.cmp_exact);
     }
     __device__ __forceinline__ int place(const Ctx& c, int, int k, int rank) const
     {
@@ -310,13 +323,13 @@ struct PolFirst {
         const SetInfo s = gld(sets + g);
         if (c.n_lo > 0) {
             record_vertex(bitmap, vidx, vlist, info, c.sbase + 1 + a.cnt[0], s.clid);
-            child(4 * g + 0, c.e[0], a.best[0], c.sbase + 1, a.cnt[0]);
-            child(4 * g + 1, c.e[1], a.best[1], c.sbase + 1 + c.n_lo - a.cnt[1], a.cnt[1]);
+            child(4 * g + 0, c.edge(0), a.best[0], c.sbase + 1, a.cnt[0]);
+            child(4 * g + 1, c.edge(1), a.best[1], c.sbase + 1 + c.n_lo - a.cnt[1], a.cnt[1]);
         }
         if (c.n_up > 0) {
             record_vertex(bitmap, vidx, vlist, info, c.sbase + 2 + c.n_lo + a.cnt[2], s.cuid);
-            child(4 * g + 2, c.e[2], a.best[2], c.sbase + 2 + c.n_lo, a.cnt[2]);
-            child(4 * g + 3, c.e[3], a.best[3], c.sbase + 2 + c.n_lo + c.n_up - a.cnt[3], a.cnt[3]);
+            child(4 * g + 2, c.edge(2), a.best[2], c.sbase + 2 + c.n_lo, a.cnt[2]);
+            child(4 * g + 3, c.edge(3), a.best[3], c.sbase + 2 + c.n_lo + c.n_up - a.cnt[3], a.cnt[3]);
         }
     }
 };
@@ -332,9 +345,15 @@ struct PolPass {
     // lane-parallel path
     static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = true;
     static constexpr int ROWS = kRows;
+    // A, C, B as loaded; the edges A->C and C->B are rebuilt where used
+    // (cheaper than keeping them live across the streaming loop)
     struct Ctx {
-        Edge e[2];  // A->C, C->B
+        float ax, ay, cx, cy, bx, by;
         int off, len, vstart;
+        __device__ __forceinline__ Edge edge(int k) const
+        {
+            return k == 0 ? make_edge(ax, ay, cx, cy) : make_edge(cx, cy, bx, by);
+        }
     };
     const Seg* segs;
     const int* seg_cid;
@@ -362,8 +381,7 @@ struct PolPass {
     {
         const Seg s = gld(segs + g);
         Ctx c;
-        c.e[0] = make_edge(s.ax, s.ay, s.cx, s.cy);
-        c.e[1] = make_edge(s.cx, s.cy, s.bx, s.by);
+        c.ax = s.ax; c.ay = s.ay; c.cx = s.cx; c.cy = s.cy; c.bx = s.bx; c.by = s.by;
         c.off = s.off;
         c.len = s.len;
         c.vstart = gld(vstart + g);
@@ -378,11 +396,12 @@ struct PolPass {
     {
         const bool f64 = fp64 != 0;
         ctr.orient += 2;
-        const Orient32 o1 = orient32(c.e[0], x, y);
-        const Orient32 o2 = orient32(c.e[1], x, y);
+        const Edge e0 = c.edge(0), e1 = c.edge(1);
+        const Orient32 o1 = orient32(e0, x, y);
+        const Orient32 o2 = orient32(e1, x, y);
         int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
-        settle(s1, s1 == 0, c.e[0], x, y, ctr.orient_exact);
-        settle(s2, s1 >= 0 && s2 == 0, c.e[1], x, y, ctr.orient_exact);
+        settle(s1, s1 == 0, e0, x, y, ctr.orient_exact);
+        settle(s2, s1 >= 0 && s2 == 0, e1, x, y, ctr.orient_exact);
         const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
         k = make_cand(in1 ? o1 : o2, x, y, id);
         return in1 ? 0 : (in2 ? 1 : kNone);
@@ -393,7 +412,7 @@ struct PolPass {
     }
     __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters& ctr) const
     {
-        return sqh::beats(c.e[k], P, Q, fp64 != 0, ctr.cmp_exact);
+        return sqh::beats(c.edge(k), P, Q, fp64 != 0, ctr.cmp_exact);
     }
     __device__ __forceinline__ int place(const Ctx& c, int, int k, int rank) const
     {
@@ -415,8 +434,8 @@ struct PolPass {
     __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
     {
         record_vertex(bitmap, vidx, vlist, info, c.off + a.cnt[0], gld(seg_cid + g));
-        child(2 * g + 0, c.e[0], a.best[0], c.off, a.cnt[0]);
-        child(2 * g + 1, c.e[1], a.best[1], c.off + c.len - a.cnt[1], a.cnt[1]);
+        child(2 * g + 0, c.edge(0), a.best[0], c.off, a.cnt[0]);
+        child(2 * g + 1, c.edge(1), a.best[1], c.off + c.len - a.cnt[1], a.cnt[1]);
     }
 };
 
@@ -526,7 +545,8 @@ constexpr int kMaxChunks = 512;  // workgroups of the persistent grid (upper bou
 constexpr int kMaxInfoPasses = 256;
 constexpr int kMaxPasses = 1 << 16;
 constexpr int kMaxStamps = 1024;
-constexpr int kTailPoints = 1 << 16;   // default: below this many points one workgroup finishes the passes
+constexpr int kTailPoints = 1 << 13;   // default: passes over at most this many points ...
+constexpr int kTailSegs = 256;         // ... and segments run on one workgroup (no grid barriers)
 constexpr int kSmallHull = 2048;       // single hulls up to this size are emitted by one workgroup
 
 // info block written for the host
@@ -885,8 +905,10 @@ __device__ __forceinline__ void run_pass(const HullArgs& a, int cur, int S, int 
                                          Pair* red, Counters& ctr)
 {
     const int nxt = cur ^ 1;
+    // the vertex list only serves the one-workgroup emission of a single hull
+    int2* vl = (a.vcap > 0 && a.G == 1) ? a.vlist : nullptr;
     PolPass pol{a.segs[cur], a.seg_cid[cur], a.vstart[cur], a.X[cur], a.Y[cur], a.I[cur], a.X[nxt], a.Y[nxt],
-                a.I[nxt], a.recs, a.rec_cid, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, S};
+                a.I[nxt], a.recs, a.rec_cid, a.bitmap, a.vidx, vl, a.info, a.fp64, S};
     phase_compact<PolPass, SINGLE>(a, pol, V, 2, a.segs[nxt], a.seg_cid[nxt], a.vstart[nxt], a.sv + 2 * nxt,
                                    Pair{0, 0}, sh, red, ctr);
 }
@@ -1019,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
                 if (b == 0 && threadIdx.x == 0) atomicOr(a.err, kErrBounds);
                 break;
             }
-            if (V <= a.tail_points) {
+            if (V <= a.tail_points && S <= kTailSegs) {
                 // few points left: workgroup 0 finishes the passes alone
                 tail = true;
                 if (b == 0) {

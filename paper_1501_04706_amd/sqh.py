@@ -131,6 +131,10 @@ def load() -> ctypes.CDLL:
     lib.sqh_engine_admit.restype = c_int
     lib.sqh_engine_step.argtypes = [vp, c_int, vp]
     lib.sqh_engine_step.restype = c_int
+    lib.sqh_engine_launch.argtypes = [vp, c_int, vp]
+    lib.sqh_engine_launch.restype = c_int
+    lib.sqh_engine_finish.argtypes = [vp]
+    lib.sqh_engine_finish.restype = c_int
     lib.sqh_engine_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), vp, i64, ctypes.POINTER(i64)]
     lib.sqh_engine_poll.restype = c_int
     lib.sqh_engine_status.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -282,6 +286,14 @@ def sqh_engine_admit(engine: int, xy, n: int, tag: int, stream=None) -> int:
 
 def sqh_engine_step(engine: int, max_passes: int, stream=None) -> int:
     return load().sqh_engine_step(engine, max_passes, _stream_handle(stream))
+
+
+def sqh_engine_launch(engine: int, max_passes: int, stream=None) -> int:
+    return load().sqh_engine_launch(engine, max_passes, _stream_handle(stream))
+
+
+def sqh_engine_finish(engine: int) -> int:
+    return load().sqh_engine_finish(engine)
 
 
 def sqh_engine_poll(engine: int, h_out, cap: int):
@@ -436,6 +448,21 @@ class Engine:
         rc = sqh_engine_step(self.e, max_passes, stream)
         if rc < 0:
             raise SqhError(rc, "sqh_engine_step")
+        return rc
+
+    def launch(self, max_passes: int = 4, stream=None) -> bool:
+        """Enqueue a step; False if there is nothing to do."""
+        rc = sqh_engine_launch(self.e, max_passes, stream)
+        if rc == SQH_ENOTFOUND:
+            return False
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_engine_launch")
+        return True
+
+    def finish(self) -> int:
+        rc = sqh_engine_finish(self.e)
+        if rc < 0:
+            raise SqhError(rc, "sqh_engine_finish")
         return rc
 
     def poll(self):

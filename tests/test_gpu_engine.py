@@ -171,3 +171,42 @@ def test_engine_device_input_and_fp64(H):
     finally:
         E.close()
         H2.close()
+
+
+def test_engine_admit_while_step_in_flight(H):
+    import torch
+    say("engine: admissions on a copy stream overlap launched steps")
+    reqs = requests(13, 40, 50, 400_000)
+    pinned = [torch.from_numpy(xy).pin_memory() for xy in reqs]
+    copy = torch.cuda.Stream()
+    E = H.engine(1 << 22, 128, 1 << 20)
+    try:
+        results = {}
+        nxt = 0
+        inflight = False
+        rounds = 0
+        while len(results) < len(reqs):
+            # admit two per round: these copies run while the launched step computes
+            for _ in range(2):
+                if nxt < len(reqs) and E.admit(pinned[nxt], nxt, stream=copy):
+                    nxt += 1
+            if inflight:
+                E.finish()
+                while True:
+                    r = E.poll()
+                    if r is None:
+                        break
+                    results[r[0]] = r[1]
+            inflight = E.launch(2)
+            rounds += 1
+            assert rounds < 2000
+        with pytest.raises(sqh.SqhError):
+            # a second launch while one is in flight is refused
+            assert E.admit(pinned[0], 999, stream=copy)
+            E.launch(2)
+            E.launch(2)
+        E.finish()
+        for i, xy in enumerate(reqs):
+            assert [int(v) for v in results[i]] == expect_hull(xy), i
+    finally:
+        E.close()

@@ -175,3 +175,28 @@ def test_errors(H):
     assert [int(v) for v in out.cpu().numpy()] == expect[:5]
     rc, h = sqh.sqh_hull(H.ctx, t, len(xy), out, 5, ws, 1000)
     assert rc == sqh.SQH_ENOMEM
+
+
+@pytest.mark.parametrize("kind", ["square", "disk", "circle", "grid"])
+def test_full_size_20m(H, kind):
+    # the benchmarked size and launch configuration; the C oracle takes ~10 s
+    say(f"{kind} n=20000000 seed 0 (full size)")
+    xy = workloads.make(kind, 20_000_000, 0)
+    import torch
+    t = torch.from_numpy(xy).cuda()
+    got = H.hull(t).cpu().numpy()
+    assert [int(v) for v in got] == [int(v) for v in oracle.c_hull(xy)]
+
+
+def test_full_batch_4096_sets(H):
+    # the benchmarked batch: 4096 sets rescaled to ~64M points; every set's
+    # hull is checked against the oracle
+    import torch
+    say("batch 4096 sets, ~64M points")
+    b = workloads.batch(4096, seed=4, total=64_000_000)
+    out, out_off = H.hull_batched(torch.from_numpy(b.xy).cuda(), torch.from_numpy(b.offsets).cuda())
+    out = out.cpu().numpy()
+    out_off = out_off.cpu().numpy()
+    for s in range(b.nsets):
+        got = out[out_off[s]:out_off[s + 1]]
+        assert [int(v) for v in got] == [int(v) for v in oracle.c_hull(b.set(s))], s

@@ -168,7 +168,10 @@ int sqh_autotune(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, int6
 
 /*
  * The context's tuning table as JSON,
- *   {"entries": [{"log2n": K, "grid": G, "tail": T}, ...]}
+ *   {"entries": [{"log2n": K, "grid": G, "tail": T}, ...], "engine_grid": E}
+ * ("engine_grid", present when set, is the number of workgroups of a serving
+ * engine step; by default a step leaves 1/8 of the compute units free so
+ * that the copies of the next step's admissions can run beside it)
  * written NUL-terminated into host buffer `buf` of `len` bytes (truncated
  * if short; buf may be NULL). Returns the length the full text needs,
  * including the NUL, or SQH_EINVAL.
@@ -177,9 +180,11 @@ int sqh_get_tuning(const sqh_ctx *ctx, char *buf, size_t len);
 
 /*
  * Replace the context's tuning table with the entries of `json` (the format
- * of sqh_get_tuning; an empty list restores the built-in shape). Rejects the
- * whole text with SQH_EINVAL if an entry lacks a key or has grid outside
- * [1, co-resident workgroups of this device] or a negative tail.
+ * of sqh_get_tuning; an empty list restores the built-in shape; a missing
+ * "engine_grid" restores the engine default). Rejects the whole text with
+ * SQH_EINVAL if an entry lacks a key or has grid outside [1, co-resident
+ * workgroups of this device] or a negative tail, or engine_grid is outside
+ * [1, co-resident workgroups].
  */
 int sqh_set_tuning(sqh_ctx *ctx, const char *json);
 

@@ -101,6 +101,7 @@ struct sqh_ctx {
     static constexpr int kMaxTune = 40;
     TuneEntry tune[kMaxTune];
     int ntune = 0;
+    int engine_grid = 0;  // workgroups of an engine step (0: all but 1/8 of the co-resident ones)
 };
 
 struct sqh_graph {
@@ -608,7 +609,9 @@ int sqh_get_tuning(const sqh_ctx* c, char* buf, size_t len)
     for (int i = 0; i < c->ntune; ++i)
         n += snprintf(tmp + n, sizeof tmp - n, "%s{\"log2n\": %d, \"grid\": %d, \"tail\": %d}", i ? ", " : "",
                       c->tune[i].log2n, c->tune[i].grid, c->tune[i].tail);
-    n += snprintf(tmp + n, sizeof tmp - n, "]}");
+    n += snprintf(tmp + n, sizeof tmp - n, "]");
+    if (c->engine_grid > 0) n += snprintf(tmp + n, sizeof tmp - n, ", \"engine_grid\": %d", c->engine_grid);
+    n += snprintf(tmp + n, sizeof tmp - n, "}");
     if (buf && len > 0) {
         const size_t k = std::min<size_t>(len - 1, (size_t)n);
         memcpy(buf, tmp, k);
@@ -638,8 +641,13 @@ int sqh_set_tuning(sqh_ctx* c, const char* json)
         if (nt >= sqh_ctx::kMaxTune) return SQH_EINVAL;
         t[nt++] = TuneEntry{(int)k, (int)g, (int)tl};
     }
+    long eg = 0;
+    const char* after = close + 1;
+    if (read_int_key(after, after + strlen(after), "engine_grid", eg) && (eg < 1 || eg > c->max_grid))
+        return SQH_EINVAL;
     memcpy(c->tune, t, sizeof(TuneEntry) * nt);
     c->ntune = nt;
+    c->engine_grid = (int)eg;
     return SQH_OK;
 }
 
@@ -847,7 +855,12 @@ int sqh_engine_launch(sqh_engine* e, int max_passes, void* stream)
     HIP_OK(hipMemcpyAsync(at(L.res_base), up_rbase, sizeof(int) * (size_t)nres, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(at(L.res_n), up_rn, sizeof(int) * (size_t)nres, hipMemcpyHostToDevice, st));
 
-    const TuneEntry tu = pick_tuning(c, e->stage_used > 0 ? e->stage_used : 1);
+    // An engine step leaves 1/8 of the compute units free by default: the
+    // copies of the next step's admissions run as copy kernels, which cannot
+    // start while the persistent kernel holds every compute unit.
+    TuneEntry tu = pick_tuning(c, e->stage_used > 0 ? e->stage_used : 1);
+    tu.grid = c->engine_grid > 0 ? std::min(c->engine_grid, c->max_grid)
+                                 : std::max(1, c->max_grid - c->max_grid / 8);
     HullArgs a{};
     a.xy = reinterpret_cast<const float2*>(A + L.stage) + (size_t)e->side * L.SC;
     a.N = (int)e->stage_used;

@@ -69,11 +69,13 @@ def test_engine_alone_equals_oracle(H):
         E.close()
 
 
-@pytest.mark.parametrize("max_passes", [1, 2, 5])
-def test_engine_mix_staggered(H, max_passes):
+@pytest.mark.parametrize("max_passes,engine_grid", [(1, 0), (2, 64), (5, 128)])
+def test_engine_mix_staggered(H, max_passes, engine_grid):
     # new requests join every step while older ones still have segments
-    say(f"engine: staggered mix, {max_passes} passes per step")
+    say(f"engine: staggered mix, {max_passes} passes per step, engine grid {engine_grid}")
     reqs = requests(2 + max_passes, 60, 3, 150_000)
+    if engine_grid:
+        H.set_tuning('{"entries": [], "engine_grid": %d}' % engine_grid)
     E = H.engine(1 << 21, 256)
     try:
         results = {}
@@ -97,6 +99,7 @@ def test_engine_mix_staggered(H, max_passes):
         assert E.status()["free_slots"] == E.slots
     finally:
         E.close()
+        H.set_tuning('{"entries": []}')
 
 
 def test_engine_admission_by_footprint(H):

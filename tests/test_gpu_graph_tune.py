@@ -73,8 +73,13 @@ def test_launch_shapes_same_hull(H, grid_frac, tail):
 def test_tuning_text_rejected(H):
     say("tuning text validation")
     for bad in ['', '{}', '{"entries": [{"log2n": 3}]}', '{"entries": [{"log2n": 3, "grid": 0, "tail": 1}]}',
-                '{"entries": [{"log2n": 3, "grid": 1, "tail": -1}]}', '{"entries": [{"log2n": 3, "grid": 1']:
+                '{"entries": [{"log2n": 3, "grid": 1, "tail": -1}]}', '{"entries": [{"log2n": 3, "grid": 1',
+                '{"entries": [], "engine_grid": 0}', '{"entries": [], "engine_grid": 100000}']:
         assert sqh.sqh_set_tuning(H.ctx, bad) == sqh.SQH_EINVAL, bad
+    assert H.tuning() == '{"entries": []}'
+    H.set_tuning('{"entries": [], "engine_grid": 17}')
+    assert H.tuning() == '{"entries": [], "engine_grid": 17}'
+    H.set_tuning('{"entries": []}')
     assert H.tuning() == '{"entries": []}'
 
 

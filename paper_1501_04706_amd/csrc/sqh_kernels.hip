@@ -541,7 +541,7 @@ __device__ __forceinline__ Pair block_excl_scan(Pair v, Pair* red, Pair* tot)
     return Pair{off.a + inc.a - v.a, off.b + inc.b - v.b};
 }
 
-constexpr int kMaxChunks = 512;  // workgroups of the persistent grid (upper bound)
+constexpr int kMaxChunks = 256;  // workgroups of the persistent grid (upper bound: one per CU)
 constexpr int kMaxInfoPasses = 256;
 constexpr int kMaxPasses = 1 << 16;
 constexpr int kMaxStamps = 1024;
@@ -922,6 +922,247 @@ __device__ __forceinline__ void note_pass(const HullArgs& a, int pass, int S, in
     }
 }
 
+// ---- the last passes of a single hull or batch, in LDS ------------------
+//
+// Once at most kTinyPoints points in at most kTinySegs segments are left,
+// workgroup 0 copies them into LDS and runs every remaining pass there, one
+// point per thread: each point is classified against A->C and C->B of its
+// segment (section 4.4.3); a segmented scan along the points (shuffles in a
+// wave, then across waves) gives every point its rank in its child and the
+// last point of a segment both children's counts and farthest points
+// (section 4.4.1); a block scan places the children (section 4.4.4), and the
+// points move to their child in the other LDS buffer. Slot ranges and vertex
+// keys follow the pass in global memory exactly (child (A,C) keeps the front
+// of the parent's slots, (C,B) the back, C's key is off + |(A,C)|), so the
+// emission is unchanged. Points keep no slot order inside a child here: only
+// the slot ranges matter for the keys.
+constexpr int kTinyPoints = 1024;  // at most this many points: the rest runs in LDS (one per thread)
+
+struct TinySeg {
+    float ax, ay, bx, by, cx, cy;  // A, B and the farthest point C
+    int off, len, cid, vs;         // slot range, C's index, first point in LDS
+};
+
+// Segments are single-buffered (S <= V <= kTinyPoints: every segment holds
+// a point, and a pass keeps fewer points than it reads), points
+// double-buffered.
+struct TinyLds {
+    float x[2][kTinyPoints], y[2][kTinyPoints];
+    int id[2][kTinyPoints];
+    TinySeg seg[kTinyPoints + 1];  // + the sentinel: seg[S].vs = V
+    float bx[kTinyPoints][2], by[kTinyPoints][2];
+    int bid[kTinyPoints][2], cnt[kTinyPoints][2], pbase[kTinyPoints][2];
+};
+
+__device__ __forceinline__ Cand tiny_wave_max(const Edge& E, Cand v, bool fp64, Counters& ctr)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Cand o = shfl_xor_cand(v, m);
+        if (beats(E, o, v, fp64, ctr.cmp_exact)) v = o;
+    }
+    return v;
+}
+
+// Workgroup 0 only. Reads the pass state of buffer `cur` (S segments, V <=
+// kTinyPoints points) and runs passes `pass`, pass + 1, ... until no
+// segment is left.
+__device__ __forceinline__ void tiny_passes(const HullArgs& a, int cur, int pass, TinyLds& L, Pair* red,
+                                            Counters& ctr)
+{
+    const int t = (int)threadIdx.x, lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const bool f64 = a.fp64 != 0;
+    int2* vl = (a.vcap > 0 && a.G == 1) ? a.vlist : nullptr;
+    int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
+    // load the segment table and the points
+    for (int s = t; s < S; s += kBlock) {
+        const Seg g = gld(a.segs[cur] + s);
+        TinySeg& q = L.seg[s];
+        q.ax = g.ax; q.ay = g.ay; q.bx = g.bx; q.by = g.by; q.cx = g.cx; q.cy = g.cy;
+        q.off = g.off; q.len = g.len;
+        q.cid = gld(a.seg_cid[cur] + s);
+        q.vs = gld(a.vstart[cur] + s);
+    }
+    if (t == 0) L.seg[S].vs = V;
+    __syncthreads();
+    if (t < V) {
+        int lo = 0, hi = S - 1;  // segment of position t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.seg[mid].vs <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int p = L.seg[lo].off + (t - L.seg[lo].vs);
+        L.x[0][t] = gld(a.X[cur] + p);
+        L.y[0][t] = gld(a.Y[cur] + p);
+        L.id[0][t] = gld(a.I[cur] + p);
+    }
+    __syncthreads();
+    int c = 0;
+    for (;; ++pass) {
+        note_pass(a, pass, S, V);
+        if (S <= 0) break;
+        // 1. point t: its segment, its child (A,C) = 0 / (C,B) = 1 / none
+        const bool valid = t < V;
+        int st = S;  // lanes without a point form their own segment
+        if (valid) {
+            int lo = 0, hi = S - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.seg[mid].vs <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            st = lo;
+        }
+        const int vs = valid ? L.seg[st].vs : t;
+        Edge e0, e1;
+        float px = 0.0f, py = 0.0f;
+        int pid = 0;
+        {
+            const TinySeg& q = L.seg[valid ? st : 0];
+            e0 = make_edge(q.ax, q.ay, q.cx, q.cy);
+            e1 = make_edge(q.cx, q.cy, q.bx, q.by);
+        }
+        if (valid) { px = L.x[c][t]; py = L.y[c][t]; pid = L.id[c][t]; }
+        ctr.orient += valid ? 2 : 0;
+        const Orient32 o1 = orient32(e0, px, py);
+        const Orient32 o2 = orient32(e1, px, py);
+        int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
+        settle(s1, valid && s1 == 0, e0, px, py, ctr.orient_exact);
+        settle(s2, valid && s1 >= 0 && s2 == 0, e1, px, py, ctr.orient_exact);
+        const bool in0 = valid && s1 < 0, in1 = valid && !(s1 < 0) && s2 < 0;
+        const int k = in0 ? 0 : (in1 ? 1 : -1);
+        // 2. segmented inclusive scan of (count, farthest) per child along
+        // the points: within the wave by shuffles, then across waves
+        const Cand cand = make_cand(in0 ? o1 : o2, px, py, pid);
+        int c0 = in0 ? 1 : 0, c1 = in1 ? 1 : 0;
+        Cand b0 = in0 ? cand : no_cand(), b1 = in1 ? cand : no_cand();
+        const int wstart = t - lane;
+        bool flag = vs >= t;  // a segment starts here (or no point)
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int oc0 = __shfl_up(c0, d), oc1 = __shfl_up(c1, d);
+            const Cand ob0 = shfl_up_cand(b0, d), ob1 = shfl_up_cand(b1, d);
+            const int of = __shfl_up(flag ? 1 : 0, d);
+            if (lane >= d && !flag) {
+                c0 += oc0;
+                c1 += oc1;
+                if (beats(e0, ob0, b0, f64, ctr.cmp_exact)) b0 = ob0;
+                if (beats(e1, ob1, b1, f64, ctr.cmp_exact)) b1 = ob1;
+                flag = of != 0;
+            }
+        }
+        // wave totals: lane 63 holds the aggregate of the segment running
+        // out of the wave, since its start or the wave's start (flag false)
+        __shared__ int wc[kWaves][2], wflag[kWaves], wseg[kWaves];
+        __shared__ Cand wb[kWaves][2];
+        if (lane == 63) {
+            wc[w][0] = c0; wc[w][1] = c1;
+            wb[w][0] = b0; wb[w][1] = b1;
+            wflag[w] = flag ? 1 : 0;
+            wseg[w] = st;
+        }
+        __syncthreads();
+        if (w == 0 && lane < kWaves) {
+            // R[v] = wflag[v] ? own[v] : R[v-1] (+) own[v] (the same segment)
+            const int v = lane;
+            int r0 = wc[v][0], r1 = wc[v][1];
+            Cand q0 = wb[v][0], q1 = wb[v][1];
+            bool f = wflag[v] != 0 || v == 0;
+            const int sv = wseg[v];
+            Edge f0 = e0, f1 = e1;
+            if (sv < S) {
+                const TinySeg& q = L.seg[sv];
+                f0 = make_edge(q.ax, q.ay, q.cx, q.cy);
+                f1 = make_edge(q.cx, q.cy, q.bx, q.by);
+            }
+            for (int d = 1; d < kWaves; d <<= 1) {
+                const int o0 = __shfl_up(r0, d), o1 = __shfl_up(r1, d);
+                const Cand p0 = shfl_up_cand(q0, d), p1 = shfl_up_cand(q1, d);
+                const int of = __shfl_up(f ? 1 : 0, d);
+                if (v >= d && !f) {
+                    r0 += o0;
+                    r1 += o1;
+                    if (beats(f0, p0, q0, f64, ctr.cmp_exact)) q0 = p0;
+                    if (beats(f1, p1, q1, f64, ctr.cmp_exact)) q1 = p1;
+                    f = of != 0;
+                }
+            }
+            wc[v][0] = r0; wc[v][1] = r1;
+            wb[v][0] = q0; wb[v][1] = q1;
+        }
+        __syncthreads();
+        if (w > 0 && valid && vs < wstart) {
+            // the segment started in an earlier wave: add what came before
+            c0 += wc[w - 1][0];
+            c1 += wc[w - 1][1];
+            if (beats(e0, wb[w - 1][0], b0, f64, ctr.cmp_exact)) b0 = wb[w - 1][0];
+            if (beats(e1, wb[w - 1][1], b1, f64, ctr.cmp_exact)) b1 = wb[w - 1][1];
+        }
+        // the last point of a segment holds its totals
+        if (valid && t == L.seg[st + 1].vs - 1) {
+            L.cnt[st][0] = c0; L.cnt[st][1] = c1;
+            L.bx[st][0] = b0.x; L.by[st][0] = b0.y; L.bid[st][0] = b0.id;
+            L.bx[st][1] = b1.x; L.by[st][1] = b1.y; L.bid[st][1] = b1.id;
+        }
+        const int rank = k == 0 ? c0 - 1 : c1 - 1;  // earlier points of the same child
+        __syncthreads();
+        // 3. children of segment t: their points' base and their table index
+        // (S <= kTinyPoints = kBlock: one thread per segment)
+        TinySeg mine = {};
+        int n0 = 0, n1 = 0;
+        if (t < S) {
+            mine = L.seg[t];
+            n0 = L.cnt[t][0];
+            n1 = L.cnt[t][1];
+        }
+        Pair tot;
+        const Pair ex = block_excl_scan(Pair{n0 + n1, (n0 > 0) + (n1 > 0)}, red, &tot);
+        if (t < S) {
+            L.pbase[t][0] = ex.a;
+            L.pbase[t][1] = ex.a + n0;
+            // C is a vertex: its key is the first slot after the (A,C) points
+            record_vertex(a.bitmap, a.vidx, vl, a.info, mine.off + n0, mine.cid);
+        }
+        __syncthreads();
+        // 4. move every kept point to its child
+        if (k >= 0) {
+            const int dst = L.pbase[st][k] + rank;
+            L.x[c ^ 1][dst] = px;
+            L.y[c ^ 1][dst] = py;
+            L.id[c ^ 1][dst] = pid;
+        }
+        __syncthreads();
+        // 5. the child table replaces the parents: (A,C) keeps the front of
+        // the parent's slots, (C,B) the back
+        if (t < S) {
+            int j = ex.b;
+            if (n0 > 0) {
+                TinySeg& q = L.seg[j++];
+                q.ax = mine.ax; q.ay = mine.ay; q.bx = mine.cx; q.by = mine.cy;
+                q.cx = L.bx[t][0]; q.cy = L.by[t][0]; q.cid = L.bid[t][0];
+                q.off = mine.off; q.len = n0; q.vs = ex.a;
+            }
+            if (n1 > 0) {
+                TinySeg& q = L.seg[j];
+                q.ax = mine.cx; q.ay = mine.cy; q.bx = mine.bx; q.by = mine.by;
+                q.cx = L.bx[t][1]; q.cy = L.by[t][1]; q.cid = L.bid[t][1];
+                q.off = mine.off + mine.len - n1; q.len = n1; q.vs = ex.a + n0;
+            }
+        }
+        if (t == 0) L.seg[tot.b].vs = tot.a;
+        __syncthreads();
+        stamp(a, 100 + pass);
+        S = tot.b;
+        V = tot.a;
+        c ^= 1;
+    }
+    if (t == 0) {
+        a.sv[2 * cur] = 0;
+        a.sv[2 * cur + 1] = 0;
+    }
+}
+
 // Ordered emission of a single hull with few vertices by one workgroup: the
 // rank of a vertex is the number of vertices with a smaller key.
 __device__ __forceinline__ void emit_small(const HullArgs& a, int h, int2* lds)
@@ -997,7 +1238,12 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
 {
     __shared__ ChunkShared<PolFirst> sh_first;
     __shared__ Pair red[kWaves];
-    __shared__ int2 vl[kSmallHull];
+    // the vertex list of the one-workgroup emission and the LDS of the last
+    // passes are never live together
+    __shared__ uint4 lds_tail[(sizeof(TinyLds) > sizeof(int2) * kSmallHull ? sizeof(TinyLds)
+                                                                          : sizeof(int2) * kSmallHull) / 16 + 1];
+    int2* vl = reinterpret_cast<int2*>(lds_tail);
+    TinyLds* tiny = reinterpret_cast<TinyLds*>(lds_tail);
     auto& shF = sh_first;
     auto& shS = *reinterpret_cast<ChunkShared<PolSeed>*>(&sh_first);
     auto& shP = *reinterpret_cast<ChunkShared<PolSplit>*>(&sh_first);
@@ -1041,12 +1287,17 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
                 if (b == 0 && threadIdx.x == 0) atomicOr(a.err, kErrBounds);
                 break;
             }
-            if (V <= a.tail_points && S <= kTailSegs) {
-                // few points left: workgroup 0 finishes the passes alone
+            if ((V <= a.tail_points && S <= kTailSegs) || V <= kTinyPoints) {
+                // few points left: workgroup 0 finishes the passes alone,
+                // the last ones in LDS
                 tail = true;
                 if (b == 0) {
                     for (int p = pass;; ++p) {
                         const int S2 = ld_flag(a.sv + 2 * cur), V2 = ld_flag(a.sv + 2 * cur + 1);
+                        if (S2 > 0 && V2 <= kTinyPoints) {
+                            tiny_passes(a, cur, p, *tiny, red, ctr);
+                            break;
+                        }
                         note_pass(a, p, S2, V2);
                         if (S2 <= 0) break;
                         if (p >= kMaxPasses) {

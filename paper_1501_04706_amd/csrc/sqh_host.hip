@@ -195,7 +195,7 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.stats = static_cast<uint32_t*>(at(L.stats));
     a.info = static_cast<HullInfo*>(at(L.info));
     a.fp64 = ctx->fp64;
-    a.timing = ctx->trace ? 2 : 1;
+    a.timing = ctx->trace == 1 ? 2 : (ctx->trace == 2 ? 3 : 1);
     a.tail_points = tu.tail;
     const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
     reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
@@ -494,7 +494,7 @@ int sqh_create(sqh_ctx** out, int device)
     c->max_grid = std::min(kMaxGrid, per_cu * c->cus);
     {
         const char* t = getenv("SQH_TRACE");
-        c->trace = t && t[0] == '1';
+        c->trace = t ? atoi(t) : 0;  // 1: seed and split, 2: first compaction and first pass
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->evk) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess ||

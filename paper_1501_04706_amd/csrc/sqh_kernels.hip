@@ -557,6 +557,7 @@ struct HullInfo {
     int vcount;
     int vcap;     // capacity of the vertex list
     int cur_out;  // engine: survivor buffer holding the segments left after the step
+    int pass_traced;  // timing 3: the first grid pass has been traced
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -623,9 +624,13 @@ __device__ __forceinline__ void stamp(const HullArgs& a, int tag)
     }
 }
 
-__device__ __forceinline__ void trace(const HullArgs& a, int slot)
+// Per-workgroup timestamps: timing 2 traces the seed (slots 0-3) and the
+// first split (4-7); timing 3 the first compaction (0-3) and the first pass
+// (4-7): start of A, end of A, after the barrier, end of B(C).
+__device__ __forceinline__ void trace(const HullArgs& a, int mode, int slot)
 {
-    if (a.timing == 2 && threadIdx.x == 0 && blockIdx.x < kMaxChunks) a.info->trace[blockIdx.x][slot] = wall_clock64();
+    if (a.timing == mode && threadIdx.x == 0 && blockIdx.x < kMaxChunks)
+        a.info->trace[blockIdx.x][slot] = wall_clock64();
 }
 
 __device__ __forceinline__ int chunk_len(int P, int nb)
@@ -874,13 +879,13 @@ __device__ __forceinline__ void phase_reduce(const HullArgs& a, const Pol& pol, 
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     int glo, ghi;
     const int t0 = Pol::COUNTS ? 4 : 0;
-    trace(a, t0 + 0);
+    trace(a, 2, t0 + 0);
     phase_step_a(a, pol, P, nb, b, 0, sh, red, ctr, glo, ghi);
-    trace(a, t0 + 1);
+    trace(a, 2, t0 + 1);
     grid_sync(a.bar, a.err);
-    trace(a, t0 + 2);
+    trace(a, 2, t0 + 2);
     phase_step_b(a, pol, P, nb, b, sh, ctr);
-    trace(a, t0 + 3);
+    trace(a, 2, t0 + 3);
     grid_sync(a.bar, a.err);
 }
 
@@ -892,12 +897,20 @@ __device__ __forceinline__ void phase_compact(const HullArgs& a, const Pol& pol,
 {
     const int nb = SINGLE ? 1 : (int)gridDim.x, b = SINGLE ? 0 : (int)blockIdx.x;
     int glo, ghi;
+    // trace: the first compaction in slots 0-3, the first grid pass in 4-7
+    const int t0 = (Pol::NB == 4) ? 0 : 4;
+    const bool tr = a.timing == 3 && !SINGLE && (Pol::NB == 4 || !a.info->pass_traced);
+    if (tr) trace(a, 3, t0 + 0);
     phase_step_a(a, pol, P, nb, b, mul, sh, red, ctr, glo, ghi);
+    if (tr) trace(a, 3, t0 + 1);
     if (SINGLE) __syncthreads();
     else grid_sync(a.bar, a.err);
+    if (tr) trace(a, 3, t0 + 2);
     phase_step_bc(a, pol, P, nb, b, mul, glo, ghi, segs, seg_cid, vstart, sv, tb, sh, red, ctr);
+    if (tr) trace(a, 3, t0 + 3);
     if (SINGLE) __syncthreads();
     else grid_sync(a.bar, a.err);
+    if (tr && Pol::NB == 2 && b == 0 && threadIdx.x == 0 && a.timing == 3) a.info->pass_traced = 1;
 }
 
 template <class Pol, bool SINGLE>
@@ -1376,6 +1389,7 @@ __global__ void k_reset(HullArgs a)
         a.info->first_v = 0;
         a.info->vcount = 0;
         a.info->vcap = a.vcap;
+        a.info->pass_traced = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;

@@ -58,6 +58,11 @@ extern "C" {
 #define SQH_FP32_FILTER 0  /* float32 filter, exact float64 expansion on failure */
 #define SQH_FP64_ONLY   1  /* every predicate evaluated exactly in float64 */
 
+/* Pre-filter of single hulls (sqh_set_prefilter). */
+#define SQH_PREFILTER_NONE    0  /* the plain method */
+#define SQH_PREFILTER_QUAD    1  /* the paper's first mode: extremes in x and y */
+#define SQH_PREFILTER_OCTAGON 2  /* also the extremes of x + y and x - y */
+
 typedef struct sqh_ctx sqh_ctx;
 
 #define SQH_MAX_TIMED_PASSES 64
@@ -80,6 +85,8 @@ typedef struct sqh_stats {
     double  ms_total;         /* device time of the whole call: workspace reset + hull kernel */
     double  ms_kernel;        /* the persistent hull kernel alone */
     double  ms_seed, ms_split, ms_first, ms_pass, ms_emit;  /* phases of the hull kernel */
+    double  ms_prefilter;     /* the pre-filter's two phases (extremes, compaction) */
+    int64_t prefilter_points; /* points kept by the pre-filter plus its corners; -1: not run */
     int64_t pass_points[SQH_MAX_TIMED_PASSES];    /* points entering pass k */
     int64_t pass_segments[SQH_MAX_TIMED_PASSES];  /* segments in pass k */
     double  pass_ms[SQH_MAX_TIMED_PASSES];        /* kernel time of pass k */
@@ -99,6 +106,20 @@ void sqh_destroy(sqh_ctx *ctx);
 /* Select SQH_FP32_FILTER (default) or SQH_FP64_ONLY. Outputs are identical;
  * only speed and the exact-path counters differ. */
 int sqh_set_precision(sqh_ctx *ctx, int mode);
+
+/*
+ * Pre-filter for sqh_hull (batched calls and the engine ignore it): the
+ * paper's first mode (section 4.2, Table 2's Mode 1) finds the extreme
+ * points in x and y and discards the points inside their quadrilateral
+ * before the first split; SQH_PREFILTER_OCTAGON adds the extremes of x + y
+ * and x - y. Each extreme is a hull vertex (ties: see the kernels), the
+ * points strictly outside the polygon are compacted stably and the method
+ * runs on them plus the corners. The output is identical to the plain
+ * method. Inputs with a coordinate above 2^125 in magnitude (where x + y
+ * could overflow float32 and the exact comparison of sums fails) run the
+ * plain method. Returns SQH_OK or SQH_EINVAL.
+ */
+int sqh_set_prefilter(sqh_ctx *ctx, int mode);
 
 /*
  * Device workspace, in bytes, needed by sqh_hull (n_sets = 1) or

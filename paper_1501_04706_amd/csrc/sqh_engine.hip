@@ -58,18 +58,19 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(HullArgs a)
     stamp(a, 0);
     if (a.G > 0) {
         {
-            PolSeed pol{a.xy, a.gstart, a.sets, a.err, a.bad, a.G};
+            PolSeed pol{a.xy, a.gstart, a.sets, a.err, nullptr, a.bad, a.G};
             phase_reduce(a, pol, a.N, shS, red, ctr);
         }
         stamp(a, 1);
         {
-            PolSplit pol{a.xy, a.gstart, a.sbase, a.bad, a.sets, a.bitmap, a.vidx, nullptr, a.info, a.fp64, a.G};
+            PolSplit pol{a.xy, a.gstart, a.sbase, a.bad, nullptr, a.sets, a.bitmap, a.vidx, nullptr, a.info, a.fp64,
+                         a.G};
             phase_reduce(a, pol, a.N, shP, red, ctr);
         }
         stamp(a, 2);
         {
-            PolFirst pol{a.xy,      a.gstart, a.sbase, a.bad,   a.sets, a.X[cur], a.Y[cur], a.I[cur], a.recs,
-                         a.rec_cid, a.bitmap, a.vidx,  nullptr, a.info, a.fp64,   a.G};
+            PolFirst pol{a.xy,   a.gstart,  a.sbase,  a.bad,  nullptr, a.sets, a.X[cur], a.Y[cur], a.I[cur],
+                         a.recs, a.rec_cid, a.bitmap, a.vidx, nullptr, a.info, a.fp64,   a.G};
             phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[cur], a.seg_cid[cur], a.vstart[cur],
                                            a.sv + 2 * cur, res, shF, red, ctr);
         }

@@ -31,6 +31,7 @@ struct Layout {
     size_t x[2], y[2], id[2];
     size_t gstart, sets, recs, rec_cid, segs[2], seg_cid[2], vstart[2];
     size_t bitmap, vidx, vlist, wprefix, slots, ctab, bar, err, stats, sv, info;
+    size_t oct, huge, xy2, ids2, gs2;
     int64_t vcap;
     size_t bytes;
 };
@@ -68,13 +69,19 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     L.vcap = std::min<int64_t>(N + 8, kSmallHull);
     L.vlist = take(sizeof(int2) * (size_t)L.vcap);
     L.wprefix = take(sizeof(int) * (size_t)L.W);
-    L.slots = take(sizeof(ChunkSlot<4>) * (size_t)kMaxGrid);
+    L.slots = take(sizeof(ChunkSlot<8>) * (size_t)kMaxGrid);
     L.ctab = take(sizeof(Pair) * (size_t)kMaxGrid);
     L.bar = take(sizeof(GridBar));
     L.err = take(sizeof(int));
     L.stats = take(sizeof(uint32_t) * 4 * kStatSlots);
     L.sv = take(sizeof(int) * 4);
     L.info = take(sizeof(HullInfo));
+    // pre-filter of a single hull: corners, the kept subset and its indices
+    L.oct = take(sizeof(float) * 24);
+    L.huge = take(sizeof(int));
+    L.xy2 = take(sizeof(float2) * (size_t)std::max<int64_t>(N, 1));
+    L.ids2 = take(sizeof(int) * (size_t)std::max<int64_t>(N, 1));
+    L.gs2 = take(sizeof(int) * 2);
     L.bytes = o;
     return true;
 }
@@ -102,6 +109,7 @@ struct sqh_ctx {
     TuneEntry tune[kMaxTune];
     int ntune = 0;
     int engine_grid = 0;  // workgroups of an engine step (0: all but 1/8 of the co-resident ones)
+    int prefilter = 0;    // SQH_PREFILTER_*
 };
 
 struct sqh_graph {
@@ -197,6 +205,12 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.fp64 = ctx->fp64;
     a.timing = ctx->trace == 1 ? 2 : (ctx->trace == 2 ? 3 : 1);
     a.tail_points = tu.tail;
+    a.prefilter = nsets == 1 ? ctx->prefilter : 0;
+    a.oct = static_cast<float*>(at(L.oct));
+    a.huge = static_cast<int*>(at(L.huge));
+    a.xy2 = static_cast<float2*>(at(L.xy2));
+    a.ids2 = static_cast<int*>(at(L.ids2));
+    a.gs2 = static_cast<int*>(at(L.gs2));
     const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
     reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
     return SQH_OK;
@@ -210,6 +224,9 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
+    if (a.prefilter && a.G == 1 && a.N > 0)
+        HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_prefilter), dim3(grid), dim3(kBlock), argv,
+                                          0, st));
     HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull), dim3(grid), dim3(kBlock), argv, 0, st));
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
@@ -251,6 +268,7 @@ int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t
     phase_times(hi, S);
     const int64_t h = hi.h_total;
     S.hull_size = h;
+    S.prefilter_points = hi.prefilter_n;
     if (timed) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
@@ -271,7 +289,8 @@ void phase_times(const HullInfo& hi, sqh_stats& S)
     auto dt = [&](int i) { return (double)(hi.stamp[i] - hi.stamp[i - 1]) * tick_ms; };
     for (int i = 1; i < hi.nstamps && i < kMaxStamps; ++i) {
         const int tag = hi.stamp_tag[i];
-        if (tag == 1) S.ms_seed += dt(i);
+        if (tag == 5) S.ms_prefilter += dt(i);
+        else if (tag == 1) S.ms_seed += dt(i);
         else if (tag == 2) S.ms_split += dt(i);
         else if (tag == 3) S.ms_first += dt(i);
         else if (tag == 4) S.ms_emit += dt(i);
@@ -376,7 +395,7 @@ bool make_eng_layout(int64_t K, int64_t R, int64_t SC, EngLayout& L)
     L.res_h = take(sizeof(int) * (size_t)R);
     L.stage = take(sizeof(float2) * (size_t)(2 * SC));  // two halves: one per step in flight
     L.vlist = take(sizeof(int2));
-    L.slots = take(sizeof(ChunkSlot<4>) * (size_t)kMaxGrid);
+    L.slots = take(sizeof(ChunkSlot<8>) * (size_t)kMaxGrid);
     L.ctab = take(sizeof(Pair) * (size_t)kMaxGrid);
     L.bar = take(sizeof(GridBar));
     L.err = take(sizeof(int));
@@ -519,6 +538,13 @@ void sqh_destroy(sqh_ctx* c)
     if (c->hstats) (void)hipHostFree(c->hstats);
     if (c->herr) (void)hipHostFree(c->herr);
     delete c;
+}
+
+int sqh_set_prefilter(sqh_ctx* c, int mode)
+{
+    if (!c || mode < SQH_PREFILTER_NONE || mode > SQH_PREFILTER_OCTAGON) return SQH_EINVAL;
+    c->prefilter = mode;
+    return SQH_OK;
 }
 
 int sqh_set_precision(sqh_ctx* c, int mode)
@@ -674,7 +700,7 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     }
     // two kernel nodes: the workspace reset, then the persistent kernel,
     // marked cooperative so that every workgroup is resident at once
-    hipGraphNode_t n_reset = nullptr, n_hull = nullptr;
+    hipGraphNode_t n_reset = nullptr, n_pre = nullptr, n_hull = nullptr;
     void* argv[] = {static_cast<void*>(&g->args)};
     hipKernelNodeParams kp{};
     kp.func = reinterpret_cast<void*>(k_reset);
@@ -687,13 +713,20 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     hp.func = reinterpret_cast<void*>(k_hull);
     hp.gridDim = dim3(tu.grid);
     hp.blockDim = dim3(kBlock);
+    hipKernelNodeParams pp = hp;
+    pp.func = reinterpret_cast<void*>(k_prefilter);
+    const bool pre = g->args.prefilter && g->args.G == 1 && g->args.N > 0;
     hipKernelNodeAttrValue coop{};
     coop.cooperative = 1;
-    if (hipGraphCreate(&g->graph, 0) != hipSuccess ||
-        hipGraphAddKernelNode(&n_reset, g->graph, nullptr, 0, &kp) != hipSuccess ||
-        hipGraphAddKernelNode(&n_hull, g->graph, &n_reset, 1, &hp) != hipSuccess ||
-        hipGraphKernelNodeSetAttribute(n_hull, hipKernelNodeAttributeCooperative, &coop) != hipSuccess ||
-        hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    bool ok = hipGraphCreate(&g->graph, 0) == hipSuccess &&
+              hipGraphAddKernelNode(&n_reset, g->graph, nullptr, 0, &kp) == hipSuccess;
+    if (ok && pre)
+        ok = hipGraphAddKernelNode(&n_pre, g->graph, &n_reset, 1, &pp) == hipSuccess &&
+             hipGraphKernelNodeSetAttribute(n_pre, hipKernelNodeAttributeCooperative, &coop) == hipSuccess;
+    ok = ok && hipGraphAddKernelNode(&n_hull, g->graph, pre ? &n_pre : &n_reset, 1, &hp) == hipSuccess &&
+         hipGraphKernelNodeSetAttribute(n_hull, hipKernelNodeAttributeCooperative, &coop) == hipSuccess &&
+         hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
         sqh_graph_destroy(g);
         return SQH_EDEVICE;
     }

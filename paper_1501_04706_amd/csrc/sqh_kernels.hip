@@ -62,6 +62,7 @@ struct PolSeed {
     const int* gstart;
     SetInfo* sets;
     int* err;
+    const int* ids;  // null, or each position's input index (a pre-filtered subset)
     int* bad;  // null, or one flag per set raised by a non-finite coordinate
     int G;
 
@@ -73,7 +74,7 @@ struct PolSeed {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = q - c.base;
+        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
     }
     __device__ __forceinline__ int classify(const Ctx&, int g, int q, float x, float y, int id, Cand& k, Counters&) const
     {
@@ -111,6 +112,223 @@ struct PolSeed {
     }
 };
 
+// ====================================================== pre-filter ==
+// The paper's first mode (section 4.2) drops the points inside the
+// quadrilateral of the extreme points in x and y before the first split;
+// the octagon adds the extremes of x + y and x - y. Every extreme is taken
+// with a tie rule that makes it a hull vertex, so the polygon's vertices are
+// hull vertices in counter-clockwise order, every other hull vertex lies
+// strictly outside the polygon, and the hull of (points strictly outside) +
+// (polygon vertices) is the hull of all points.
+//
+// Directions, counter-clockwise from the lexicographic minimum:
+//   0 min (x, y)         1 min x + y (ties: min x)   2 min y (ties: max x)
+//   3 max x - y (max x)  4 max (x, y)                5 max x + y (max x)
+//   6 max y (ties: min x) 7 min x - y (min x)
+// Coincident points: the lowest index. The sums are compared exactly as
+// float32 TwoSum pairs (s, e) with s + e = x +- y, which needs |x|, |y| <=
+// 2^125 (no overflow); larger inputs skip the pre-filter.
+constexpr float kPrefilterMax = 4.2535295865117308e37f;  // 2^125
+
+__device__ __forceinline__ void two_sum32(float a, float b, float& s, float& e)
+{
+    const float x = a + b;
+    const float bv = x - a;
+    const float av = x - bv;
+    e = (a - av) + (b - bv);
+    s = x;
+}
+
+// sign of key(P) - key(Q), exactly, for key = x + sgn * y: the rounded sums
+// decide when they differ (rounding is monotone); equal rounded sums are
+// split by their exact rounding errors
+__device__ __forceinline__ int cmp_sum(const Cand& P, const Cand& Q, float sgn)
+{
+    const float ps = P.x + sgn * P.y, qs = Q.x + sgn * Q.y;
+    if (ps != qs) return ps > qs ? 1 : -1;
+    float s, pe, qe;
+    two_sum32(P.x, sgn * P.y, s, pe);
+    two_sum32(Q.x, sgn * Q.y, s, qe);
+    if (pe != qe) return pe > qe ? 1 : -1;
+    return 0;
+}
+
+struct PolExt8 {
+    static constexpr int NB = 8;
+    static constexpr bool COUNTS = false, SCATTER = false, MULTI = true, MIDDLE = false;
+    static constexpr int ROWS = kRows;
+    struct Ctx {
+        int base;
+    };
+    const float2* xy;
+    const int* gstart;
+    float* oct;  // per set: 8 x (x, y, index)
+    int* err;
+    int* huge;   // raised when a coordinate exceeds the exact-sum range
+    int G;
+
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
+    __device__ __forceinline__ Ctx ctx(int g) const { return Ctx{gld(gstart + g)}; }
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    {
+        const float2 v = gld(xy + q);
+        x = v.x; y = v.y; id = q - c.base;
+    }
+    __device__ __forceinline__ int classify(const Ctx&, int, int q, float x, float y, int id, Cand& k, Counters&) const
+    {
+        if (!(isfinite(x) && isfinite(y))) {
+            atomicOr(err, kErrNonFinite);
+            return 0;
+        }
+        if (fabsf(x) > kPrefilterMax || fabsf(y) > kPrefilterMax) atomicOr(huge, 1);
+        k.a = 0.0f; k.w = 0.0f; k.x = x; k.y = y; k.id = id;
+        return 0xff;  // a candidate in every direction
+    }
+    // 1 if P beats Q in direction k (a total order: ties end at the index)
+    __device__ __forceinline__ int beats_fast(const Ctx&, int k, const Cand& P, const Cand& Q) const
+    {
+        if (Q.id < 0) return P.id >= 0 ? 1 : 0;
+        if (P.id < 0) return 0;
+        int c;
+        switch (k) {
+        case 0: c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : (P.y != Q.y ? (P.y < Q.y ? 1 : -1) : 0); break;
+        case 1: c = -cmp_sum(P, Q, 1.0f); if (!c) c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0; break;
+        case 2: c = P.y != Q.y ? (P.y < Q.y ? 1 : -1) : (P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0); break;
+        case 3: c = cmp_sum(P, Q, -1.0f); if (!c) c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0; break;
+        case 4: c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : (P.y != Q.y ? (P.y > Q.y ? 1 : -1) : 0); break;
+        case 5: c = cmp_sum(P, Q, 1.0f); if (!c) c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0; break;
+        case 6: c = P.y != Q.y ? (P.y > Q.y ? 1 : -1) : (P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0); break;
+        default: c = -cmp_sum(P, Q, -1.0f); if (!c) c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0; break;
+        }
+        if (c == 0) c = P.id < Q.id ? 1 : -1;  // coincident: the lowest index
+        return c > 0 ? 1 : 0;
+    }
+    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters&) const
+    {
+        return beats_fast(c, k, P, Q) > 0;
+    }
+    __device__ __forceinline__ int place(const Ctx&, int, int, int) const { return 0; }
+    __device__ __forceinline__ void store(int, float, float, int) const {}
+    __device__ __forceinline__ void finalize(const Ctx&, int g, const Agg<NB>& a) const
+    {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            gst(oct + 24 * g + 3 * k + 0, a.best[k].x);
+            gst(oct + 24 * g + 3 * k + 1, a.best[k].y);
+            gst(oct + 24 * g + 3 * k + 2, __int_as_float(a.best[k].id));
+        }
+    }
+};
+
+// Stable compaction of one set's points outside the polygon. The polygon's
+// distinct corners come first in the subset (positions 0 .. nv-1), then the
+// kept points in input order: a coincident copy of a corner can then never
+// precede the corner, which holds the lowest index of its position. A point
+// is kept when the float32 filter finds it strictly right of an edge, or
+// cannot decide: keeping a point inside or on the polygon does not change
+// the hull, so no exact evaluation is needed here.
+struct PolKeep {
+    static constexpr int NB = 1;
+    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = false;
+    static constexpr int ROWS = kRows;
+    // The corners in direction order; coincident neighbours give zero-length
+    // edges, which are skipped.
+    struct Ctx {
+        float vx[8], vy[8];
+        int vid[8];    // the corners' indices (they enter the subset once, first)
+        int base, nv;  // first read position; distinct corners
+    };
+    const float2* xy;
+    const int* gstart;
+    const float* oct;
+    float2* xy2;
+    int* ids2;
+    int* gs2;
+    int quad;  // 1: the four axis directions only
+    int G;
+
+    __device__ __forceinline__ int num_groups() const { return G; }
+    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
+    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
+    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
+    __device__ __forceinline__ int corner_id(int g, int k) const
+    {
+        return __float_as_int(gld(oct + 24 * g + 3 * k + 2));
+    }
+    // k is a direction in use whose corner no earlier direction in use has
+    __device__ __forceinline__ bool distinct(int g, int k) const
+    {
+        if (quad && (k & 1)) return false;
+        const int id = corner_id(g, k);
+        bool dup = false;
+        for (int j = 0; j < k; ++j) dup = dup || ((!quad || !(j & 1)) && corner_id(g, j) == id);
+        return !dup;
+    }
+    __device__ __forceinline__ Ctx ctx(int g) const
+    {
+        Ctx c;
+        c.base = gld(gstart + g);
+        c.nv = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            // the quadrilateral repeats each axis corner in the next direction
+            const int d = quad ? (k & ~1) : k;
+            c.vx[k] = gld(oct + 24 * g + 3 * d);
+            c.vy[k] = gld(oct + 24 * g + 3 * d + 1);
+            c.vid[k] = corner_id(g, d);
+            c.nv += distinct(g, k) ? 1 : 0;
+        }
+        return c;
+    }
+    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
+    {
+        const float2 v = gld(xy + q);
+        x = v.x; y = v.y; id = q - c.base;
+    }
+    __device__ __forceinline__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
+    {
+        // subset size = corners + kept <= n: the corners are not kept again
+        bool corner = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) corner = corner || id == c.vid[i];
+        bool keep = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = (i + 1) & 7;
+            if (c.vx[i] == c.vx[j] && c.vy[i] == c.vy[j]) continue;  // zero-length edge
+            const Edge E = make_edge(c.vx[i], c.vy[i], c.vx[j], c.vy[j]);
+            const Orient32 o = orient32(E, x, y);
+            ++ctr.orient;
+            keep = keep || !(o.d > o.es);  // not certainly left of the edge: outside, or undecided
+        }
+        k = no_cand();
+        return keep && !corner ? 0 : kNone;
+    }
+    __device__ __forceinline__ int beats_fast(const Ctx&, int, const Cand&, const Cand&) const { return 0; }
+    __device__ __forceinline__ bool beats(const Ctx&, int, const Cand&, const Cand&, Counters&) const { return false; }
+    __device__ __forceinline__ int place(const Ctx& c, int, int, int rank) const { return c.nv + rank; }
+    __device__ __forceinline__ void store(int dst, float x, float y, int id) const
+    {
+        gst(xy2 + dst, make_float2(x, y));
+        gst(ids2 + dst, id);
+    }
+    __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
+    {
+        int n = 0;
+        for (int k = 0; k < 8; ++k) {
+            if (!distinct(g, k)) continue;
+            gst(xy2 + n, make_float2(gld(oct + 24 * g + 3 * k), gld(oct + 24 * g + 3 * k + 1)));
+            gst(ids2 + n, corner_id(g, k));
+            ++n;
+        }
+        gst(gs2 + 0, 0);
+        gst(gs2 + 1, c.nv + a.cnt[0]);
+    }
+};
+
 // =========================================================== k_split ==
 struct PolSplit {
     static constexpr int NB = 2;
@@ -126,6 +344,7 @@ struct PolSplit {
     const int* gstart;
     const int* sbase;
     const int* bad;  // null, or sets to skip (non-finite input)
+    const int* ids;  // null, or each position's input index (a pre-filtered subset)
     SetInfo* sets;
     uint64_t* bitmap;
     int* vidx;
@@ -152,7 +371,7 @@ struct PolSplit {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = q - c.base;
+        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
     }
     // lower side: strictly right of A->B; upper side: strictly left of A->B
     // (= strictly right of B->A). Points on the line -- A, B, duplicates and
@@ -226,6 +445,7 @@ struct PolFirst {
     const int* gstart;
     const int* sbase;
     const int* bad;
+    const int* ids;  // null, or each position's input index (a pre-filtered subset)
     const SetInfo* sets;
     float* X;
     float* Y;
@@ -259,7 +479,7 @@ struct PolFirst {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = q - c.base;
+        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
     }
     // Section 4.4.3: a point of segment (A,B) with farthest point C is kept
     // for child (A,C) if strictly right of A->C, for child (C,B) if strictly
@@ -558,6 +778,8 @@ struct HullInfo {
     int vcap;     // capacity of the vertex list
     int cur_out;  // engine: survivor buffer holding the segments left after the step
     int pass_traced;  // timing 3: the first grid pass has been traced
+    int prefilter_n;  // points kept by the pre-filter (+ corners), -1 if it did not run
+    int keep_n;       // pre-filter: kept points appended so far
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -610,7 +832,15 @@ struct HullArgs {
     int* res_h;              // nres: hull size of a set finished in this step
     int* hout;               // slot-indexed hull output of finished sets
     int* bad;                // G: new set had a non-finite coordinate
+    // pre-filter (single hulls): 0 none, 1 quadrilateral, 2 octagon
+    int prefilter;
+    float* oct;              // polygon corners: 8 x (x, y, index)
+    int* huge;               // a coordinate is outside the exact-sum range
+    float2* xy2;             // the kept subset: points ...
+    int* ids2;               // ... and their input indices
+    int* gs2;                // {0, subset size}
 };
+
 
 __device__ __forceinline__ void stamp(const HullArgs& a, int tag)
 {
@@ -871,13 +1101,19 @@ __device__ __forceinline__ void phase_step_bc(const HullArgs& a, const Pol& pol,
     process_chunk<Pol, kModeScatter>(pol, cb, ce, glo, ghi, sh, ctr);
 }
 
-// A reduction phase on the whole grid.
-template <class Pol>
+// A reduction phase on the whole grid, or (SINGLE) on workgroup 0 alone,
+// whose one chunk holds every group whole, so that step A finalises them all.
+template <class Pol, bool SINGLE = false>
 __device__ __forceinline__ void phase_reduce(const HullArgs& a, const Pol& pol, int P, ChunkShared<Pol>& sh,
                                              Pair* red, Counters& ctr)
 {
-    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nb = SINGLE ? 1 : (int)gridDim.x, b = SINGLE ? 0 : (int)blockIdx.x;
     int glo, ghi;
+    if (SINGLE) {
+        phase_step_a(a, pol, P, nb, b, 0, sh, red, ctr, glo, ghi);
+        __syncthreads();
+        return;
+    }
     const int t0 = Pol::COUNTS ? 4 : 0;
     trace(a, 2, t0 + 0);
     phase_step_a(a, pol, P, nb, b, 0, sh, red, ctr, glo, ghi);
@@ -1195,11 +1431,11 @@ __device__ __forceinline__ void emit_small(const HullArgs& a, int h, int2* lds)
 // Ordered emission on the whole grid: vertex keys are the set bits of the
 // bitmap; the rank of a key among all keys is its output position (keys
 // increase along each set's ring and sets are stored in order).
-__device__ __forceinline__ void emit_grid(const HullArgs& a, Pair* red)
+// W: bitmap words holding the keys
+__device__ __forceinline__ void emit_grid(const HullArgs& a, Pair* red, int W)
 {
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int gtid = b * kBlock + (int)threadIdx.x, gstride = nb * kBlock;
-    const int W = a.W;
     const int CHw = (W + nb - 1) / nb;
     const int wb = min(b * CHw, W), we = min(wb + CHw, W);
     Pair mine = {0, 0};
@@ -1247,6 +1483,64 @@ __device__ __forceinline__ void emit_grid(const HullArgs& a, Pair* red)
     }
 }
 
+constexpr int kSmallInput = 1 << 15;  // single hulls up to this size run on one workgroup
+
+// Seed, first split and first compaction (on the grid, or SINGLE on
+// workgroup 0 alone). False if the input was rejected (non-finite).
+template <bool SINGLE>
+__device__ __forceinline__ bool first_phases(const HullArgs& a, const float2* in_xy, int* in_gstart,
+                                             const int* in_ids, int in_n,
+                                             ChunkShared<PolSeed>& shS, ChunkShared<PolSplit>& shP,
+                                             ChunkShared<PolFirst>& shF, Pair* red, Counters& ctr)
+{
+    // ---- seed: lexmin / lexmax of every set
+    {
+        PolSeed pol{in_xy, in_gstart, a.sets, a.err, in_ids, nullptr, a.G};
+        phase_reduce<PolSeed, SINGLE>(a, pol, in_n, shS, red, ctr);
+    }
+    stamp(a, 1);
+    // flags raised before the barrier decide the path; every workgroup sees them
+    if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) return false;
+    // ---- first split: side counts and farthest point of each side
+    {
+        PolSplit pol{in_xy,  in_gstart, in_gstart, nullptr, in_ids, a.sets, a.bitmap,
+                     a.vidx, a.vlist,   a.info,    a.fp64,  a.G};
+        phase_reduce<PolSplit, SINGLE>(a, pol, in_n, shP, red, ctr);
+    }
+    stamp(a, 2);
+    // ---- first compaction into four child segments per set
+    {
+        PolFirst pol{in_xy,  in_gstart, in_gstart, nullptr, in_ids, a.sets,  a.X[0], a.Y[0], a.I[0],
+                     a.recs, a.rec_cid, a.bitmap,  a.vidx,  a.vlist, a.info, a.fp64, a.G};
+        phase_compact<PolFirst, SINGLE>(a, pol, in_n, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, Pair{0, 0},
+                                        shF, red, ctr);
+    }
+    stamp(a, 3);
+    return true;
+}
+
+// The remaining passes on workgroup 0 alone, the last ones in LDS.
+__device__ __forceinline__ void tail_passes(const HullArgs& a, int cur, int pass, TinyLds& tiny,
+                                            ChunkShared<PolPass>& shQ, Pair* red, Counters& ctr)
+{
+    for (int p = pass;; ++p) {
+        const int S2 = ld_flag(a.sv + 2 * cur), V2 = ld_flag(a.sv + 2 * cur + 1);
+        if (S2 > 0 && V2 <= kTinyPoints) {
+            tiny_passes(a, cur, p, tiny, red, ctr);
+            break;
+        }
+        note_pass(a, p, S2, V2);
+        if (S2 <= 0) break;
+        if (p >= kMaxPasses) {
+            if (threadIdx.x == 0) atomicOr(a.err, kErrBounds);
+            break;
+        }
+        run_pass<PolPass, true>(a, cur, S2, V2, shQ, red, ctr);
+        stamp(a, 100 + p);
+        cur ^= 1;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
 {
     __shared__ ChunkShared<PolFirst> sh_first;
@@ -1265,34 +1559,40 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     const int b = (int)blockIdx.x;
     bool tail = false;
 
+    // ---- a single hull after the pre-filter (k_prefilter) runs on the kept
+    // subset, whose indices are mapped back at the emission (only these few
+    // values are redirected: the arguments stay in the kernel's argument
+    // segment)
+    const int n2 = (a.prefilter && a.G == 1 && a.N > 0) ? ld_flag(&a.info->prefilter_n) : -1;
+    const bool sub = n2 >= 0 && n2 <= a.N;  // (the subset never exceeds the input)
+    const float2* in_xy = sub ? a.xy2 : a.xy;
+    int* in_gstart = sub ? a.gs2 : a.gstart;
+    const int* in_ids = sub ? a.ids2 : nullptr;  // the subset's points carry their input indices
+    const int in_n = sub ? n2 : a.N;
+
+    bool run_tail = false;  // this workgroup finishes the passes alone
+    int cur = 0, pass = 0;
+
     stamp(a, 0);
     if (ld_flag(a.err) & kErrBounds) goto done;  // set offsets rejected by k_reset
-    // ---- seed: lexmin / lexmax of every set
-    {
-        PolSeed pol{a.xy, a.gstart, a.sets, a.err, nullptr, a.G};
-        phase_reduce(a, pol, a.N, shS, red, ctr);
-    }
-    stamp(a, 1);
-    // flags raised before the barrier decide the path; every workgroup sees them
-    if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;
-    // ---- first split: side counts and farthest point of each side
-    {
-        PolSplit pol{a.xy, a.gstart, a.gstart, nullptr, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64, a.G};
-        phase_reduce(a, pol, a.N, shP, red, ctr);
-    }
-    stamp(a, 2);
-    // ---- first compaction into four child segments per set
-    {
-        PolFirst pol{a.xy,     a.gstart,  a.gstart, nullptr, a.sets, a.X[0], a.Y[0], a.I[0], a.recs,
-                     a.rec_cid, a.bitmap, a.vidx,   a.vlist, a.info, a.fp64, a.G};
-        phase_compact<PolFirst, false>(a, pol, a.N, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, Pair{0, 0}, shF,
-                                       red, ctr);
-    }
-    stamp(a, 3);
-    // ---- segmented passes over all segments of all sets
-    {
-        int cur = 0;
-        for (int pass = 0;; ++pass) {
+    // A single hull of few points runs on workgroup 0 alone (no grid
+    // barriers); the other workgroups wait for its emission decision.
+    if (a.G == 1 && in_n <= kSmallInput) {
+        tail = true;
+        if (b == 0) {
+            run_tail = first_phases<true>(a, in_xy, in_gstart, in_ids, in_n, shS, shP, shF, red, ctr);
+            if (!run_tail) {
+                if (threadIdx.x == 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_store(&a.bar->emit_mode, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                goto done;  // rejected input: no emission
+            }
+        }
+    } else {
+        if (!first_phases<false>(a, in_xy, in_gstart, in_ids, in_n, shS, shP, shF, red, ctr)) goto done;
+        // ---- segmented passes over all segments of all sets
+        for (;; ++pass) {
             const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
             if (b == 0) note_pass(a, pass, S, V);
             if (S <= 0) break;
@@ -1301,27 +1601,9 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
                 break;
             }
             if ((V <= a.tail_points && S <= kTailSegs) || V <= kTinyPoints) {
-                // few points left: workgroup 0 finishes the passes alone,
-                // the last ones in LDS
+                // few points left: workgroup 0 finishes the passes alone
                 tail = true;
-                if (b == 0) {
-                    for (int p = pass;; ++p) {
-                        const int S2 = ld_flag(a.sv + 2 * cur), V2 = ld_flag(a.sv + 2 * cur + 1);
-                        if (S2 > 0 && V2 <= kTinyPoints) {
-                            tiny_passes(a, cur, p, *tiny, red, ctr);
-                            break;
-                        }
-                        note_pass(a, p, S2, V2);
-                        if (S2 <= 0) break;
-                        if (p >= kMaxPasses) {
-                            if (threadIdx.x == 0) atomicOr(a.err, kErrBounds);
-                            break;
-                        }
-                        run_pass<PolPass, true>(a, cur, S2, V2, shQ, red, ctr);
-                        stamp(a, 100 + p);
-                        cur ^= 1;
-                    }
-                }
+                run_tail = b == 0;
                 break;
             }
             run_pass<PolPass, false>(a, cur, S, V, shQ, red, ctr);
@@ -1329,6 +1611,7 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
             cur ^= 1;
         }
     }
+    if (run_tail) tail_passes(a, cur, pass, *tiny, shQ, red, ctr);
     // ---- ordered emission
     {
         // workgroup 0 decides: one workgroup (single hull, few vertices) or the grid
@@ -1360,15 +1643,137 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
             }
             __syncthreads();
             mode = smode;
+            if (mode == 3u) goto done;  // workgroup 0 rejected the input
         } else {
             // the pass loop ended on a grid barrier: every workgroup can decide
             const int h = ld_flag(&a.info->vcount);
             mode = (a.G == 1 && h <= kSmallHull && h <= a.vcap) ? 1u : 2u;
         }
-        if (mode == 2u) emit_grid(a, red);
+        if (mode == 2u) emit_grid(a, red, sub ? (n2 + 63) / 64 : a.W);
     }
     stamp(a, 4);
 done:
+    flush_counters(a.stats, ctr);
+}
+
+// The kept points of one set, appended in any order (the subset's points
+// carry their input indices, so no tie rule depends on their order): each
+// workgroup streams one contiguous chunk, stages its kept points in LDS,
+// then reserves their places with one atomic add; a chunk with more kept
+// points than the stage holds streams again and writes them directly. The
+// corners go first (positions 0 .. nv-1); the subset's size goes to gs2[1]
+// and info->prefilter_n.
+constexpr int kKeepStage = 3072;
+
+__device__ __forceinline__ void keep_append(const HullArgs& a, const PolKeep& pol, Counters& ctr)
+{
+    __shared__ float2 st_xy[kKeepStage];
+    __shared__ int st_id[kKeepStage];
+    __shared__ int st_n, st_base, wcnt[kWaves];
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x, lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const PolKeep::Ctx c = pol.ctx(0);
+    const int P = a.N;
+    const int CH = chunk_len(P, nb);
+    const int cb = (int)min((long long)b * CH, (long long)P), ce = min(cb + CH, P);
+    int wb, we;
+    wave_part(cb, ce, w, wb, we);
+    if (threadIdx.x == 0) st_n = 0;
+    __syncthreads();
+    int mine = 0;  // kept points of this wave's part
+    for (int q0 = wb; q0 < we; q0 += 64) {
+        const int q = q0 + lane;
+        float x = 0.0f, y = 0.0f;
+        int id = 0;
+        bool keep = false;
+        if (q < we) {
+            Cand k;
+            pol.load(c, 0, q, x, y, id);
+            keep = pol.classify(c, 0, q, x, y, id, k, ctr) == 0;
+        }
+        const uint64_t M = __ballot(keep);
+        if (M) {
+            int off = 0;
+            if (lane == 0) off = atomicAdd(&st_n, (int)__popcll(M));
+            off = __shfl(off, 0);
+            const int r = off + __popcll(M & mask_lt(lane));
+            if (keep && r < kKeepStage) {
+                st_xy[r] = make_float2(x, y);
+                st_id[r] = id;
+            }
+            mine += __popcll(M);
+        }
+    }
+    if (lane == 0) wcnt[w] = mine;
+    __syncthreads();
+    const int n = st_n;
+    if (threadIdx.x == 0) st_base = n > 0 ? atomicAdd(&a.info->keep_n, n) : 0;
+    __syncthreads();
+    const int base = c.nv + st_base;
+    if (n <= kKeepStage) {
+        for (int i = (int)threadIdx.x; i < n; i += kBlock) {
+            gst(a.xy2 + base + i, st_xy[i]);
+            gst(a.ids2 + base + i, st_id[i]);
+        }
+    } else {
+        // too many for the stage: stream the chunk again, in wave order
+        int r = base;
+        for (int v = 0; v < w; ++v) r += wcnt[v];
+        for (int q0 = wb; q0 < we; q0 += 64) {
+            const int q = q0 + lane;
+            float x = 0.0f, y = 0.0f;
+            int id = 0;
+            bool keep = false;
+            if (q < we) {
+                Cand k;
+                pol.load(c, 0, q, x, y, id);
+                keep = pol.classify(c, 0, q, x, y, id, k, ctr) == 0;
+            }
+            const uint64_t M = __ballot(keep);
+            if (keep) {
+                const int dst = r + __popcll(M & mask_lt(lane));
+                gst(a.xy2 + dst, make_float2(x, y));
+                gst(a.ids2 + dst, id);
+            }
+            r += __popcll(M);
+        }
+    }
+    grid_sync(a.bar, a.err);
+    if (b == 0 && threadIdx.x == 0) {
+        int k = 0;
+        for (int d = 0; d < 8; ++d) {
+            if (!pol.distinct(0, d)) continue;
+            gst(a.xy2 + k, make_float2(gld(a.oct + 3 * d), gld(a.oct + 3 * d + 1)));
+            gst(a.ids2 + k, pol.corner_id(0, d));
+            ++k;
+        }
+        const int total = c.nv + ld_flag(&a.info->keep_n);
+        a.gs2[0] = 0;
+        a.gs2[1] = total;
+        a.info->prefilter_n = total;
+    }
+}
+
+// The pre-filter of a single hull (cooperative launch before k_hull, same
+// workspace): the extreme points in eight directions, then the stable
+// compaction of the points outside their polygon into (xy2, ids2). Leaves
+// the subset's size in info->prefilter_n (-1: not run, the coordinates are
+// outside the exact-sum range; a non-finite coordinate is left to k_hull's
+// seed, which reports it).
+__global__ __launch_bounds__(kBlock) void k_prefilter(HullArgs a)
+{
+    __shared__ ChunkShared<PolExt8> sh;
+    __shared__ Pair red[kWaves];
+    Counters ctr = {0u, 0u, 0u};
+    stamp(a, 0);
+    {
+        PolExt8 pol{a.xy, a.gstart, a.oct, a.err, a.huge, a.G};
+        phase_reduce(a, pol, a.N, sh, red, ctr);
+    }
+    if (!(ld_flag(a.err) & (kErrNonFinite | kErrBounds)) && !ld_flag(a.huge)) {
+        PolKeep pol{a.xy, a.gstart, a.oct, a.xy2, a.ids2, a.gs2, a.prefilter == 1 ? 1 : 0, a.G};
+        keep_append(a, pol, ctr);
+    }
+    stamp(a, 5);
     flush_counters(a.stats, ctr);
 }
 
@@ -1390,6 +1795,9 @@ __global__ void k_reset(HullArgs a)
         a.info->vcount = 0;
         a.info->vcap = a.vcap;
         a.info->pass_traced = 0;
+        a.info->prefilter_n = -1;
+        a.info->keep_n = 0;
+        if (a.huge) *a.huge = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;

@@ -25,6 +25,9 @@ SQH_ECAPACITY = -3
 SQH_EDEVICE = -4
 SQH_EBUSY = -5
 SQH_ENOTFOUND = -6
+SQH_PREFILTER_NONE = 0
+SQH_PREFILTER_QUAD = 1
+SQH_PREFILTER_OCTAGON = 2
 SQH_FP32_FILTER = 0
 SQH_FP64_ONLY = 1
 
@@ -63,6 +66,8 @@ class SqhStats(ctypes.Structure):
         ("ms_first", ctypes.c_double),
         ("ms_pass", ctypes.c_double),
         ("ms_emit", ctypes.c_double),
+        ("ms_prefilter", ctypes.c_double),
+        ("prefilter_points", ctypes.c_int64),
         ("pass_points", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
         ("pass_segments", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
         ("pass_ms", ctypes.c_double * SQH_MAX_TIMED_PASSES),
@@ -93,6 +98,8 @@ def load() -> ctypes.CDLL:
     lib.sqh_destroy.restype = None
     lib.sqh_set_precision.argtypes = [vp, c_int]
     lib.sqh_set_precision.restype = c_int
+    lib.sqh_set_prefilter.argtypes = [vp, c_int]
+    lib.sqh_set_prefilter.restype = c_int
     lib.sqh_workspace_bytes.argtypes = [i64, i64]
     lib.sqh_workspace_bytes.restype = ctypes.c_size_t
     lib.sqh_hull.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
@@ -170,6 +177,10 @@ def sqh_destroy(ctx: int) -> None:
 
 def sqh_set_precision(ctx: int, mode: int) -> int:
     return load().sqh_set_precision(ctx, mode)
+
+
+def sqh_set_prefilter(ctx: int, mode: int) -> int:
+    return load().sqh_set_prefilter(ctx, mode)
 
 
 def sqh_workspace_bytes(n_total: int, n_sets: int = 1) -> int:
@@ -337,6 +348,11 @@ class Hull:
             self.close()
         except Exception:
             pass
+
+    def set_prefilter(self, mode: int):
+        rc = sqh_set_prefilter(self.ctx, mode)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_set_prefilter")
 
     def set_precision(self, mode: int):
         rc = sqh_set_precision(self.ctx, mode)

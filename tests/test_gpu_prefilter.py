@@ -1,0 +1,112 @@
+"""GPU: the pre-filtered single hull (the paper's first mode, and its
+octagon extension) gives exactly the oracle's hull (through the C ABI)."""
+import glob
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hull_exact as he
+from paper_1501_04706_amd import sqh, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MODES = {"quad": 1, "octagon": 2}
+
+
+def say(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", params=sorted(MODES))
+def H(request):
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a HIP device"
+    h = sqh.Hull(0)
+    h.set_prefilter(MODES[request.param])
+    h.mode_name = request.param
+    yield h
+    h.close()
+
+
+def gpu_hull(H, xy):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)).to("cuda")
+    return [int(v) for v in H.hull(t).cpu().numpy()]
+
+
+def expect(xy):
+    return he.hull(xy) if len(xy) < 3000 else [int(v) for v in oracle.c_hull(xy)]
+
+
+def load_golden(path):
+    pts, hull = [], None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("hull:"):
+            hull = [int(t) for t in line.split(":")[1].split()]
+        else:
+            pts.append([float(v) for v in line.split()])
+    return np.array(pts, np.float32).reshape(-1, 2), hull
+
+
+def test_golden_and_degenerate(H):
+    say(f"{H.mode_name}: golden fixtures and degenerate sets")
+    for path in sorted(glob.glob(os.path.join(GOLDEN, "*.txt"))):
+        xy, want = load_golden(path)
+        assert gpu_hull(H, xy) == want, path
+    cases = [
+        np.zeros((0, 2), np.float32),
+        np.array([[3, 4]], np.float32),
+        np.array([[1, 1], [0, 0]], np.float32),
+        np.full((5000, 2), 0.5, np.float32),
+        np.stack([np.arange(3000), np.arange(3000) * 3], 1).astype(np.float32)[::-1].copy(),
+        np.array([[-0.0, 0.0], [0.0, -0.0], [1, 0], [0, 1]], np.float32),
+        # a thin triangle: the apex is extreme in none of the eight directions
+        np.array([[0, 0], [10, 0], [5, 1e-3], [2, 0], [7, 0]], np.float32),
+        # a square rotated by a little: every corner ties in two directions
+        np.array([[0, 0], [1, 0], [1, 1], [0, 1], [0.5, 0.5], [1, 0.5], [0.5, 1]], np.float32),
+    ]
+    for xy in cases:
+        assert gpu_hull(H, xy) == he.hull(xy), xy[:6]
+
+
+def test_small_random_grids(H):
+    rng = np.random.default_rng(321)
+    say(f"{H.mode_name}: small random grids")
+    for it in range(300):
+        n = int(rng.integers(1, 80))
+        k = int(rng.integers(1, 7))
+        xy = (rng.integers(-k, k + 1, size=(n, 2)) * 0.5).astype(np.float32)
+        assert gpu_hull(H, xy) == he.hull(xy), (it, xy.tolist())
+
+
+@pytest.mark.parametrize("n", [2049, 6144, 123457, 1_000_000])
+def test_workloads(H, n):
+    say(f"{H.mode_name}: workloads n={n}")
+    for kind in ("square", "disk", "circle", "grid"):
+        xy = workloads.make(kind, n, n + 7)
+        assert gpu_hull(H, xy) == expect(xy), kind
+        st = H.stats()
+        assert 0 <= st["prefilter_points"] <= n, st["prefilter_points"]
+
+
+def test_full_size_square_and_disk(H):
+    for kind in ("square", "disk"):
+        say(f"{H.mode_name}: {kind} n=20000000")
+        xy = workloads.make(kind, 20_000_000, 0)
+        assert gpu_hull(H, xy) == expect(xy), kind
+        assert H.stats()["prefilter_points"] < 20_000_000
+
+
+def test_huge_coordinates_run_plain(H):
+    say(f"{H.mode_name}: coordinates beyond the exact-sum range")
+    xy = workloads.disk(50_000, 9) * np.float32(3e38)
+    assert np.all(np.isfinite(xy))
+    assert gpu_hull(H, xy) == expect(xy)
+    assert H.stats()["prefilter_points"] == -1

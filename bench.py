@@ -156,6 +156,38 @@ def bench_batched(H, sqh, torch, workloads, total, steps: int, warmup: int, seed
     }
 
 
+def bench_breakdown(H, sqh, torch, workloads, steps: int = 5, warmup: int = 2) -> list:
+    """Per-phase device time of single hulls at the paper's sizes (1M .. 20M
+    points, square and disk), plain and with each pre-filter: the phase
+    times come from the kernel's own clock stamps, the total from HIP events."""
+    modes = (("plain", sqh.SQH_PREFILTER_NONE), ("quad", sqh.SQH_PREFILTER_QUAD),
+             ("octagon", sqh.SQH_PREFILTER_OCTAGON))
+    dev = torch.device("cuda", 0)
+    rows = []
+    for kind in ("square", "disk"):
+        for n in (1_000_000, 5_000_000, 10_000_000, 20_000_000):
+            xy_d = torch.from_numpy(workloads.make(kind, n, 0)).to(dev)
+            out = torch.empty(n, dtype=torch.int32, device=dev)
+            H.workspace(n, 1)
+            for name, mode in modes:
+                H.set_prefilter(mode)
+                for _ in range(warmup):
+                    H.hull(xy_d, out=out)
+                acc = {}
+                for _ in range(steps):
+                    H.hull(xy_d, out=out)
+                    st = H.stats()
+                    for k in ("ms_kernel", "ms_prefilter", "ms_seed", "ms_split", "ms_first", "ms_pass", "ms_emit"):
+                        acc[k] = acc.get(k, 0.0) + st[k] / steps
+                rows.append({"kind": kind, "n": n, "mode": name,
+                             "Mpoints_per_s": round(n / (acc["ms_kernel"] / 1000.0) / 1e6, 1),
+                             "subset": int(st["prefilter_points"]),
+                             **{k[3:]: round(v, 4) for k, v in acc.items()}})
+            H.set_prefilter(sqh.SQH_PREFILTER_NONE)
+            del xy_d, out
+    return rows
+
+
 def _percentiles(lat_ms):
     import numpy as np
     v = np.asarray(lat_ms, dtype=np.float64)
@@ -302,6 +334,8 @@ def main() -> int:
                     help="fp32: float32 filter with exact fallback; fp64: every predicate exact")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=600, help="serving requests (0: skip)")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the per-phase breakdown over sizes and pre-filter modes")
     ap.add_argument("--batch", default="64M", choices=["64M", "full", "none"],
                     help="batched comparison: 4096 sets rescaled to ~64M points, the literal "
                          "log-uniform sizes (~4.4e8 points), or skip it")
@@ -415,6 +449,8 @@ def main() -> int:
                                         steps=3, warmup=1)
     if args.serve > 0:
         line["serving"] = bench_serving(H, sqh, torch, workloads, count=args.serve)
+    if not args.no_breakdown:
+        line["breakdown"] = bench_breakdown(H, sqh, torch, workloads)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(xy)
     else:

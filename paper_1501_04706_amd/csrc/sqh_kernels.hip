@@ -258,28 +258,38 @@ struct PolKeep {
     {
         return __float_as_int(gld(oct + 24 * g + 3 * k + 2));
     }
-    // k is a direction in use whose corner no earlier direction in use has
-    __device__ __forceinline__ bool distinct(int g, int k) const
+    // corner k enters the subset: a direction in use whose corner no earlier
+    // direction in use has (the quadrilateral uses the even directions)
+    __device__ __forceinline__ static bool distinct(const int (&id)[8], int quad, int k)
     {
         if (quad && (k & 1)) return false;
-        const int id = corner_id(g, k);
         bool dup = false;
-        for (int j = 0; j < k; ++j) dup = dup || ((!quad || !(j & 1)) && corner_id(g, j) == id);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < k) dup = dup || ((!quad || !(j & 1)) && id[j] == id[k]);
         return !dup;
     }
     __device__ __forceinline__ Ctx ctx(int g) const
     {
         Ctx c;
         c.base = gld(gstart + g);
+        float ox[8], oy[8];
+        int oid[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {  // independent loads, then register work
+            ox[k] = gld(oct + 24 * g + 3 * k);
+            oy[k] = gld(oct + 24 * g + 3 * k + 1);
+            oid[k] = __float_as_int(gld(oct + 24 * g + 3 * k + 2));
+        }
         c.nv = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             // the quadrilateral repeats each axis corner in the next direction
             const int d = quad ? (k & ~1) : k;
-            c.vx[k] = gld(oct + 24 * g + 3 * d);
-            c.vy[k] = gld(oct + 24 * g + 3 * d + 1);
-            c.vid[k] = corner_id(g, d);
-            c.nv += distinct(g, k) ? 1 : 0;
+            c.vx[k] = ox[d];
+            c.vy[k] = oy[d];
+            c.vid[k] = oid[d];
+            c.nv += distinct(oid, quad, k) ? 1 : 0;
         }
         return c;
     }
@@ -315,15 +325,21 @@ struct PolKeep {
         gst(xy2 + dst, make_float2(x, y));
         gst(ids2 + dst, id);
     }
-    __device__ __forceinline__ void finalize(const Ctx& c, int g, const Agg<NB>& a) const
+    // the distinct corners, at positions 0 .. nv-1
+    __device__ __forceinline__ void write_corners(const Ctx& c) const
     {
         int n = 0;
+#pragma unroll
         for (int k = 0; k < 8; ++k) {
-            if (!distinct(g, k)) continue;
-            gst(xy2 + n, make_float2(gld(oct + 24 * g + 3 * k), gld(oct + 24 * g + 3 * k + 1)));
-            gst(ids2 + n, corner_id(g, k));
+            if (!distinct(c.vid, quad, k)) continue;
+            gst(xy2 + n, make_float2(c.vx[k], c.vy[k]));
+            gst(ids2 + n, c.vid[k]);
             ++n;
         }
+    }
+    __device__ __forceinline__ void finalize(const Ctx& c, int, const Agg<NB>& a) const
+    {
+        write_corners(c);
         gst(gs2 + 0, 0);
         gst(gs2 + 1, c.nv + a.cnt[0]);
     }
@@ -1739,13 +1755,7 @@ __device__ __forceinline__ void keep_append(const HullArgs& a, const PolKeep& po
     }
     grid_sync(a.bar, a.err);
     if (b == 0 && threadIdx.x == 0) {
-        int k = 0;
-        for (int d = 0; d < 8; ++d) {
-            if (!pol.distinct(0, d)) continue;
-            gst(a.xy2 + k, make_float2(gld(a.oct + 3 * d), gld(a.oct + 3 * d + 1)));
-            gst(a.ids2 + k, pol.corner_id(0, d));
-            ++k;
-        }
+        pol.write_corners(c);
         const int total = c.nv + ld_flag(&a.info->keep_n);
         a.gs2[0] = 0;
         a.gs2[1] = total;

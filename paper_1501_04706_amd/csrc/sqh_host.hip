@@ -216,6 +216,14 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     return SQH_OK;
 }
 
+// The persistent kernel for these arguments: the instance that reads the
+// pre-filter's subset only where the pre-filter runs.
+inline bool pre_runs(const HullArgs& a) { return a.prefilter && a.G == 1 && a.N > 0; }
+inline const void* hull_kernel(const HullArgs& a)
+{
+    return pre_runs(a) ? reinterpret_cast<const void*>(k_hull<true>) : reinterpret_cast<const void*>(k_hull<false>);
+}
+
 // Enqueue the workspace reset and the persistent kernel, bracketed by events.
 int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
 {
@@ -224,10 +232,10 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
-    if (a.prefilter && a.G == 1 && a.N > 0)
+    if (pre_runs(a))
         HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_prefilter), dim3(grid), dim3(kBlock), argv,
                                           0, st));
-    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull), dim3(grid), dim3(kBlock), argv, 0, st));
+    HIP_OK(hipLaunchCooperativeKernel(hull_kernel(a), dim3(grid), dim3(kBlock), argv, 0, st));
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
 }
@@ -503,13 +511,16 @@ int sqh_create(sqh_ctx** out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return SQH_EDEVICE; }
     c->cus = prop.multiProcessorCount;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_hull), kBlock, 0) !=
-            hipSuccess ||
-        per_cu < 1) {
+    int per_cu = 0, per_cu_pre = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_hull<false>), kBlock,
+                                                     0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pre, reinterpret_cast<const void*>(k_hull<true>), kBlock,
+                                                     0) != hipSuccess ||
+        std::min(per_cu, per_cu_pre) < 1) {
         delete c;
         return SQH_EDEVICE;
     }
+    per_cu = std::min(per_cu, per_cu_pre);
     c->max_grid = std::min(kMaxGrid, per_cu * c->cus);
     {
         const char* t = getenv("SQH_TRACE");
@@ -710,12 +721,12 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     kp.kernelParams = argv;
     kp.extra = nullptr;
     hipKernelNodeParams hp = kp;
-    hp.func = reinterpret_cast<void*>(k_hull);
+    hp.func = const_cast<void*>(hull_kernel(g->args));
     hp.gridDim = dim3(tu.grid);
     hp.blockDim = dim3(kBlock);
     hipKernelNodeParams pp = hp;
     pp.func = reinterpret_cast<void*>(k_prefilter);
-    const bool pre = g->args.prefilter && g->args.G == 1 && g->args.N > 0;
+    const bool pre = pre_runs(g->args);
     hipKernelNodeAttrValue coop{};
     coop.cooperative = 1;
     bool ok = hipGraphCreate(&g->graph, 0) == hipSuccess &&

@@ -51,7 +51,8 @@ __device__ __forceinline__ void record_vertex(uint64_t* bitmap, int* vidx, int2*
 }
 
 // ============================================================ k_seed ==
-struct PolSeed {
+template <bool IDS>
+struct PolSeedT {
     static constexpr int NB = 2;
     static constexpr bool COUNTS = false, SCATTER = false, MULTI = true, MIDDLE = false;
     static constexpr int ROWS = kRows;
@@ -62,7 +63,7 @@ struct PolSeed {
     const int* gstart;
     SetInfo* sets;
     int* err;
-    const int* ids;  // null, or each position's input index (a pre-filtered subset)
+    const int* ids;  // IDS: each position's input index (a pre-filtered subset)
     int* bad;  // null, or one flag per set raised by a non-finite coordinate
     int G;
 
@@ -74,7 +75,9 @@ struct PolSeed {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
+        x = v.x; y = v.y;
+        if constexpr (IDS) id = gld(ids + q);
+        else id = q - c.base;
     }
     __device__ __forceinline__ int classify(const Ctx&, int g, int q, float x, float y, int id, Cand& k, Counters&) const
     {
@@ -111,6 +114,7 @@ struct PolSeed {
         gst(sets + g, s);
     }
 };
+using PolSeed = PolSeedT<false>;
 
 // ====================================================== pre-filter ==
 // The paper's first mode (section 4.2) drops the points inside the
@@ -309,8 +313,7 @@ struct PolKeep {
         for (int i = 0; i < 8; ++i) {
             const int j = (i + 1) & 7;
             if (c.vx[i] == c.vx[j] && c.vy[i] == c.vy[j]) continue;  // zero-length edge
-            const Edge E = make_edge(c.vx[i], c.vy[i], c.vx[j], c.vy[j]);
-            const Orient32 o = orient32(E, x, y);
+            const Orient32 o = orient32p(c.vx[i], c.vy[i], c.vx[j], c.vy[j], x, y);
             ++ctr.orient;
             keep = keep || !(o.d > o.es);  // not certainly left of the edge: outside, or undecided
         }
@@ -346,7 +349,8 @@ struct PolKeep {
 };
 
 // =========================================================== k_split ==
-struct PolSplit {
+template <bool IDS>
+struct PolSplitT {
     static constexpr int NB = 2;
     static constexpr bool COUNTS = true, SCATTER = false, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
@@ -360,7 +364,7 @@ struct PolSplit {
     const int* gstart;
     const int* sbase;
     const int* bad;  // null, or sets to skip (non-finite input)
-    const int* ids;  // null, or each position's input index (a pre-filtered subset)
+    const int* ids;  // IDS: each position's input index (a pre-filtered subset)
     SetInfo* sets;
     uint64_t* bitmap;
     int* vidx;
@@ -387,7 +391,9 @@ struct PolSplit {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
+        x = v.x; y = v.y;
+        if constexpr (IDS) id = gld(ids + q);
+        else id = q - c.base;
     }
     // lower side: strictly right of A->B; upper side: strictly left of A->B
     // (= strictly right of B->A). Points on the line -- A, B, duplicates and
@@ -396,10 +402,9 @@ struct PolSplit {
     {
         if (c.skip) return kNone;
         ++ctr.orient;
-        const Edge ab = c.ab();
-        const Orient32 o = orient32(ab, x, y);
+        const Orient32 o = orient32p(c.ax, c.ay, c.bx, c.by, x, y);
         int sg = fast_sign(o, fp64 != 0);
-        settle(sg, sg == 0, ab, x, y, ctr.orient_exact);
+        settle_p(sg, sg == 0, c.ax, c.ay, c.bx, c.by, x, y, ctr.orient_exact);
         k.a = sg < 0 ? -o.d : o.d;
         k.w = 2.0f * o.es;
         k.x = x; k.y = y; k.id = id;
@@ -428,6 +433,7 @@ struct PolSplit {
         if (!c.skip) record_vertex(bitmap, vidx, vlist, info, c.sbase + 1 + a.cnt[0], s.bid);
     }
 };
+using PolSplit = PolSplitT<false>;
 
 // =========================================================== k_first ==
 // Slot layout of set s (base = its first slot, n_s slots):
@@ -437,7 +443,8 @@ struct PolSplit {
 //                                      from the back
 //   base+1+n_lo                        B
 //   [base+2+n_lo, base+2+n_lo+n_up)    upper side: (B,C_up) front, (C_up,A) back
-struct PolFirst {
+template <bool IDS>
+struct PolFirstT {
     static constexpr int NB = 4;
     static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = false;
     static constexpr int ROWS = kRows;
@@ -461,7 +468,7 @@ struct PolFirst {
     const int* gstart;
     const int* sbase;
     const int* bad;
-    const int* ids;  // null, or each position's input index (a pre-filtered subset)
+    const int* ids;  // IDS: each position's input index (a pre-filtered subset)
     const SetInfo* sets;
     float* X;
     float* Y;
@@ -495,7 +502,9 @@ struct PolFirst {
     __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
     {
         const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = ids ? gld(ids + q) : q - c.base;
+        x = v.x; y = v.y;
+        if constexpr (IDS) id = gld(ids + q);
+        else id = q - c.base;
     }
     // Section 4.4.3: a point of segment (A,B) with farthest point C is kept
     // for child (A,C) if strictly right of A->C, for child (C,B) if strictly
@@ -506,19 +515,20 @@ struct PolFirst {
         if (c.skip) return kNone;
         const bool f64 = fp64 != 0;
         ctr.orient += 3;
-        const Edge ab = c.ab();
-        const Orient32 o = orient32(ab, x, y);
+        const Orient32 o = orient32p(c.ax, c.ay, c.bx, c.by, x, y);
         int side = fast_sign(o, f64);
-        settle(side, side == 0, ab, x, y, ctr.orient_exact);
+        settle_p(side, side == 0, c.ax, c.ay, c.bx, c.by, x, y, ctr.orient_exact);
         const bool up = side > 0;
-        // lower side: A->C_lo, C_lo->B; upper side: B->C_up, C_up->A
-        const Edge E1 = up ? make_edge(c.bx, c.by, c.ux, c.uy) : make_edge(c.ax, c.ay, c.lx, c.ly);
-        const Edge E2 = up ? make_edge(c.ux, c.uy, c.ax, c.ay) : make_edge(c.lx, c.ly, c.bx, c.by);
-        const Orient32 o1 = orient32(E1, x, y);
-        const Orient32 o2 = orient32(E2, x, y);
+        // lower side: A->C_lo, C_lo->B; upper side: B->C_up, C_up->A; the
+        // two edges share the apex C
+        const float sx = up ? c.bx : c.ax, sy = up ? c.by : c.ay;  // first edge's start
+        const float mx = up ? c.ux : c.lx, my = up ? c.uy : c.ly;  // apex
+        const float tx = up ? c.ax : c.bx, ty = up ? c.ay : c.by;  // second edge's end
+        const Orient32 o1 = orient32p(sx, sy, mx, my, x, y);
+        const Orient32 o2 = orient32p(mx, my, tx, ty, x, y);
         int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
-        settle(s1, side != 0 && s1 == 0, E1, x, y, ctr.orient_exact);
-        settle(s2, side != 0 && s1 >= 0 && s2 == 0, E2, x, y, ctr.orient_exact);
+        settle_p(s1, side != 0 && s1 == 0, sx, sy, mx, my, x, y, ctr.orient_exact);
+        settle_p(s2, side != 0 && s1 >= 0 && s2 == 0, mx, my, tx, ty, x, y, ctr.orient_exact);
         const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
         k = make_cand(in1 ? o1 : o2, x, y, id);
         const int b = up ? 2 : 0;
@@ -569,6 +579,7 @@ struct PolFirst {
         }
     }
 };
+using PolFirst = PolFirstT<false>;
 
 // ============================================================ k_pass ==
 // Positions are virtual: segment g owns [vstart[g], vstart[g+1]) and its
@@ -632,12 +643,11 @@ struct PolPass {
     {
         const bool f64 = fp64 != 0;
         ctr.orient += 2;
-        const Edge e0 = c.edge(0), e1 = c.edge(1);
-        const Orient32 o1 = orient32(e0, x, y);
-        const Orient32 o2 = orient32(e1, x, y);
+        const Orient32 o1 = orient32p(c.ax, c.ay, c.cx, c.cy, x, y);  // A -> C
+        const Orient32 o2 = orient32p(c.cx, c.cy, c.bx, c.by, x, y);  // C -> B
         int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
-        settle(s1, s1 == 0, e0, x, y, ctr.orient_exact);
-        settle(s2, s1 >= 0 && s2 == 0, e1, x, y, ctr.orient_exact);
+        settle_p(s1, s1 == 0, c.ax, c.ay, c.cx, c.cy, x, y, ctr.orient_exact);
+        settle_p(s2, s1 >= 0 && s2 == 0, c.cx, c.cy, c.bx, c.by, x, y, ctr.orient_exact);
         const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
         k = make_cand(in1 ? o1 : o2, x, y, id);
         return in1 ? 0 : (in2 ? 1 : kNone);
@@ -1503,33 +1513,35 @@ constexpr int kSmallInput = 1 << 15;  // single hulls up to this size run on one
 
 // Seed, first split and first compaction (on the grid, or SINGLE on
 // workgroup 0 alone). False if the input was rejected (non-finite).
-template <bool SINGLE>
+template <bool SINGLE, bool IDS>
 __device__ __forceinline__ bool first_phases(const HullArgs& a, const float2* in_xy, int* in_gstart,
-                                             const int* in_ids, int in_n,
-                                             ChunkShared<PolSeed>& shS, ChunkShared<PolSplit>& shP,
-                                             ChunkShared<PolFirst>& shF, Pair* red, Counters& ctr)
+                                             const int* in_ids, int in_n, ChunkShared<PolFirst>& sh, Pair* red,
+                                             Counters& ctr)
 {
+    using Seed = PolSeedT<IDS>;
+    using Split = PolSplitT<IDS>;
+    using First = PolFirstT<IDS>;
     // ---- seed: lexmin / lexmax of every set
     {
-        PolSeed pol{in_xy, in_gstart, a.sets, a.err, in_ids, nullptr, a.G};
-        phase_reduce<PolSeed, SINGLE>(a, pol, in_n, shS, red, ctr);
+        Seed pol{in_xy, in_gstart, a.sets, a.err, in_ids, nullptr, a.G};
+        phase_reduce<Seed, SINGLE>(a, pol, in_n, *reinterpret_cast<ChunkShared<Seed>*>(&sh), red, ctr);
     }
     stamp(a, 1);
     // flags raised before the barrier decide the path; every workgroup sees them
     if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) return false;
     // ---- first split: side counts and farthest point of each side
     {
-        PolSplit pol{in_xy,  in_gstart, in_gstart, nullptr, in_ids, a.sets, a.bitmap,
-                     a.vidx, a.vlist,   a.info,    a.fp64,  a.G};
-        phase_reduce<PolSplit, SINGLE>(a, pol, in_n, shP, red, ctr);
+        Split pol{in_xy, in_gstart, in_gstart, nullptr, in_ids, a.sets, a.bitmap, a.vidx, a.vlist, a.info, a.fp64,
+                  a.G};
+        phase_reduce<Split, SINGLE>(a, pol, in_n, *reinterpret_cast<ChunkShared<Split>*>(&sh), red, ctr);
     }
     stamp(a, 2);
     // ---- first compaction into four child segments per set
     {
-        PolFirst pol{in_xy,  in_gstart, in_gstart, nullptr, in_ids, a.sets,  a.X[0], a.Y[0], a.I[0],
-                     a.recs, a.rec_cid, a.bitmap,  a.vidx,  a.vlist, a.info, a.fp64, a.G};
-        phase_compact<PolFirst, SINGLE>(a, pol, in_n, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, Pair{0, 0},
-                                        shF, red, ctr);
+        First pol{in_xy,  in_gstart, in_gstart, nullptr, in_ids, a.sets,  a.X[0], a.Y[0], a.I[0],
+                  a.recs, a.rec_cid, a.bitmap,  a.vidx,  a.vlist, a.info, a.fp64, a.G};
+        phase_compact<First, SINGLE>(a, pol, in_n, 4, a.segs[0], a.seg_cid[0], a.vstart[0], a.sv, Pair{0, 0},
+                                     *reinterpret_cast<ChunkShared<First>*>(&sh), red, ctr);
     }
     stamp(a, 3);
     return true;
@@ -1557,6 +1569,9 @@ __device__ __forceinline__ void tail_passes(const HullArgs& a, int cur, int pass
     }
 }
 
+// PRE: the launch follows k_prefilter and may run on its subset (a launch
+// without the pre-filter is built without the subset's index loads).
+template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
 {
     __shared__ ChunkShared<PolFirst> sh_first;
@@ -1579,7 +1594,7 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     // subset, whose indices are mapped back at the emission (only these few
     // values are redirected: the arguments stay in the kernel's argument
     // segment)
-    const int n2 = (a.prefilter && a.G == 1 && a.N > 0) ? ld_flag(&a.info->prefilter_n) : -1;
+    const int n2 = (PRE && a.prefilter && a.G == 1 && a.N > 0) ? ld_flag(&a.info->prefilter_n) : -1;
     const bool sub = n2 >= 0 && n2 <= a.N;  // (the subset never exceeds the input)
     const float2* in_xy = sub ? a.xy2 : a.xy;
     int* in_gstart = sub ? a.gs2 : a.gstart;
@@ -1596,7 +1611,11 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     if (a.G == 1 && in_n <= kSmallInput) {
         tail = true;
         if (b == 0) {
-            run_tail = first_phases<true>(a, in_xy, in_gstart, in_ids, in_n, shS, shP, shF, red, ctr);
+            if constexpr (PRE)
+                run_tail = sub ? first_phases<true, true>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr)
+                               : first_phases<true, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
+            else
+                run_tail = first_phases<true, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
             if (!run_tail) {
                 if (threadIdx.x == 0) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1606,7 +1625,13 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
             }
         }
     } else {
-        if (!first_phases<false>(a, in_xy, in_gstart, in_ids, in_n, shS, shP, shF, red, ctr)) goto done;
+        bool ok;
+        if constexpr (PRE)
+            ok = sub ? first_phases<false, true>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr)
+                     : first_phases<false, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
+        else
+            ok = first_phases<false, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
+        if (!ok) goto done;
         // ---- segmented passes over all segments of all sets
         for (;; ++pass) {
             const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);

@@ -118,6 +118,21 @@ __device__ __forceinline__ Orient32 orient32(const Edge& E, float px, float py)
     return r;
 }
 
+// The same for the edge o -> e given by its end points (no edge record).
+__device__ __forceinline__ Orient32 orient32p(float ox, float oy, float ex, float ey, float px, float py)
+{
+    const float dx = ex - ox, dy = ey - oy;
+    float a1 = py - oy;
+    float b1 = px - ox;
+    float P = dx * a1;
+    float Q = dy * b1;
+    Orient32 r;
+    r.d = P - Q;
+    float S = fabsf(P) + fabsf(Q);
+    r.es = S * kFilterScale + kFilterTau;
+    return r;
+}
+
 // ---- exact float64 path ---------------------------------------------------
 //
 // The product of two float32 values is exact in float64 (24+24 significand
@@ -237,6 +252,18 @@ __device__ __forceinline__ void settle(int& s, bool need, const Edge& E, float p
     if (__ballot(need)) {
         if (need) {
             s = orient_exact(E.ox, E.oy, E.ex, E.ey, px, py);
+            ++n_exact;
+        }
+    }
+}
+
+// settle() for the edge o -> e given by its end points
+__device__ __forceinline__ void settle_p(int& s, bool need, float ox, float oy, float ex, float ey, float px,
+                                         float py, uint32_t& n_exact)
+{
+    if (__ballot(need)) {
+        if (need) {
+            s = orient_exact(ox, oy, ex, ey, px, py);
             ++n_exact;
         }
     }

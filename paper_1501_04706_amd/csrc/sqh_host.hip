@@ -31,7 +31,7 @@ struct Layout {
     size_t x[2], y[2], id[2];
     size_t gstart, sets, recs, rec_cid, segs[2], seg_cid[2], vstart[2];
     size_t bitmap, vidx, vlist, wprefix, slots, ctab, bar, err, stats, sv, info;
-    size_t oct, huge, xy2, ids2, gs2;
+    size_t ext, xy2, ids2, gs2;
     int64_t vcap;
     size_t bytes;
 };
@@ -77,8 +77,7 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     L.sv = take(sizeof(int) * 4);
     L.info = take(sizeof(HullInfo));
     // pre-filter of a single hull: corners, the kept subset and its indices
-    L.oct = take(sizeof(float) * 24);
-    L.huge = take(sizeof(int));
+    L.ext = take(sizeof(uint64_t) * 8 * (size_t)kMaxGrid);
     L.xy2 = take(sizeof(float2) * (size_t)std::max<int64_t>(N, 1));
     L.ids2 = take(sizeof(int) * (size_t)std::max<int64_t>(N, 1));
     L.gs2 = take(sizeof(int) * 2);
@@ -206,8 +205,7 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.timing = ctx->trace == 1 ? 2 : (ctx->trace == 2 ? 3 : 1);
     a.tail_points = tu.tail;
     a.prefilter = nsets == 1 ? ctx->prefilter : 0;
-    a.oct = static_cast<float*>(at(L.oct));
-    a.huge = static_cast<int*>(at(L.huge));
+    a.ext = static_cast<uint64_t*>(at(L.ext));
     a.xy2 = static_cast<float2*>(at(L.xy2));
     a.ids2 = static_cast<int*>(at(L.ids2));
     a.gs2 = static_cast<int*>(at(L.gs2));

@@ -119,234 +119,183 @@ using PolSeed = PolSeedT<false>;
 // ====================================================== pre-filter ==
 // The paper's first mode (section 4.2) drops the points inside the
 // quadrilateral of the extreme points in x and y before the first split;
-// the octagon adds the extremes of x + y and x - y. Every extreme is taken
-// with a tie rule that makes it a hull vertex, so the polygon's vertices are
-// hull vertices in counter-clockwise order, every other hull vertex lies
-// strictly outside the polygon, and the hull of (points strictly outside) +
-// (polygon vertices) is the hull of all points.
+// the octagon adds the extremes of x + y and x - y.
 //
-// Directions, counter-clockwise from the lexicographic minimum:
-//   0 min (x, y)         1 min x + y (ties: min x)   2 min y (ties: max x)
-//   3 max x - y (max x)  4 max (x, y)                5 max x + y (max x)
-//   6 max y (ties: min x) 7 min x - y (min x)
-// Coincident points: the lowest index. The sums are compared exactly as
-// float32 TwoSum pairs (s, e) with s + e = x +- y, which needs |x|, |y| <=
-// 2^125 (no overflow); larger inputs skip the pre-filter.
-constexpr float kPrefilterMax = 4.2535295865117308e37f;  // 2^125
+// Corner k is, among the points whose projection on direction k is extreme,
+// the one of lowest index; the diagonal projections are the float32 sums
+// fl(x + y) and fl(x - y), and -0 counts as +0. Directions, counter-clockwise
+// from -x:
+//   0 min x   1 min x + y   2 min y   3 max x - y
+//   4 max x   5 max x + y   6 max y   7 min x - y
+// Neither the rounding nor the tie rule matters for the hull. The corners
+// are input points; a point strictly left of every edge of the closed
+// polygon through them sees each edge turn by a positive angle, so its
+// winding number is positive and it lies in the interior of the corners'
+// convex hull, hence of the input's: it is no hull vertex. A point at a
+// corner's position is on an edge that starts there, so it is never
+// certified inside; if all corners coincide there is no edge and every
+// point is kept. The subset (points not certified inside, with their input
+// indices) therefore holds every hull vertex and every copy of one, and its
+// hull, tie rules included, is the input's. "Strictly left" is certified by
+// the float32 orientation filter; an overflow in it makes the bound
+// infinite or NaN, which certifies nothing.
 
-__device__ __forceinline__ void two_sum32(float a, float b, float& s, float& e)
+// order-preserving map of a float32 onto uint32 (for non-NaN values)
+__device__ __forceinline__ uint32_t ord32(float f)
 {
-    const float x = a + b;
-    const float bv = x - a;
-    const float av = x - bv;
-    e = (a - av) + (b - bv);
-    s = x;
+    const uint32_t u = __float_as_uint(f);
+    return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
 }
 
-// sign of key(P) - key(Q), exactly, for key = x + sgn * y: the rounded sums
-// decide when they differ (rounding is monotone); equal rounded sums are
-// split by their exact rounding errors
-__device__ __forceinline__ int cmp_sum(const Cand& P, const Cand& Q, float sgn)
+// Directions 3, 4, 5, 6 take the largest projection, the others the
+// smallest. Across lanes and workgroups an extreme is carried as one 64-bit
+// key: high word the projection's order, low word the index (smallest-key
+// directions) or its complement (largest-key directions), so that the
+// extreme key names the lowest index among the extreme projections.
+constexpr uint32_t kExtMax = 0x78u;
+
+__device__ __forceinline__ bool ext_is_max(int k) { return (kExtMax >> k) & 1u; }
+__device__ __forceinline__ uint64_t ext_none(int k) { return ext_is_max(k) ? 0ull : ~0ull; }
+__device__ __forceinline__ uint64_t ext_key(int k, float v, int id)
 {
-    const float ps = P.x + sgn * P.y, qs = Q.x + sgn * Q.y;
-    if (ps != qs) return ps > qs ? 1 : -1;
-    float s, pe, qe;
-    two_sum32(P.x, sgn * P.y, s, pe);
-    two_sum32(Q.x, sgn * Q.y, s, qe);
-    if (pe != qe) return pe > qe ? 1 : -1;
-    return 0;
+    if (id < 0) return ext_none(k);
+    const uint32_t o = ord32(v + 0.0f);  // -0 -> +0
+    return ((uint64_t)o << 32) | (ext_is_max(k) ? ~(uint32_t)id : (uint32_t)id);
+}
+__device__ __forceinline__ uint64_t ext_pick(int k, uint64_t a, uint64_t b)
+{
+    return ext_is_max(k) ? (a > b ? a : b) : (a < b ? a : b);
+}
+__device__ __forceinline__ int ext_index(int k, uint64_t key)
+{
+    const uint32_t lo = (uint32_t)key;
+    return (int)(ext_is_max(k) ? ~lo : lo);
 }
 
-struct PolExt8 {
-    static constexpr int NB = 8;
-    static constexpr bool COUNTS = false, SCATTER = false, MULTI = true, MIDDLE = false;
-    static constexpr int ROWS = kRows;
-    struct Ctx {
-        int base;
-    };
-    const float2* xy;
-    const int* gstart;
-    float* oct;  // per set: 8 x (x, y, index)
-    int* err;
-    int* huge;   // raised when a coordinate exceeds the exact-sum range
-    int G;
-
-    __device__ __forceinline__ int num_groups() const { return G; }
-    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
-    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
-    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
-    __device__ __forceinline__ Ctx ctx(int g) const { return Ctx{gld(gstart + g)}; }
-    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
-    {
-        const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = q - c.base;
-    }
-    __device__ __forceinline__ int classify(const Ctx&, int, int q, float x, float y, int id, Cand& k, Counters&) const
-    {
-        if (!(isfinite(x) && isfinite(y))) {
-            atomicOr(err, kErrNonFinite);
-            return 0;
-        }
-        if (fabsf(x) > kPrefilterMax || fabsf(y) > kPrefilterMax) atomicOr(huge, 1);
-        k.a = 0.0f; k.w = 0.0f; k.x = x; k.y = y; k.id = id;
-        return 0xff;  // a candidate in every direction
-    }
-    // 1 if P beats Q in direction k (a total order: ties end at the index)
-    __device__ __forceinline__ int beats_fast(const Ctx&, int k, const Cand& P, const Cand& Q) const
-    {
-        if (Q.id < 0) return P.id >= 0 ? 1 : 0;
-        if (P.id < 0) return 0;
-        int c;
-        switch (k) {
-        case 0: c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : (P.y != Q.y ? (P.y < Q.y ? 1 : -1) : 0); break;
-        case 1: c = -cmp_sum(P, Q, 1.0f); if (!c) c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0; break;
-        case 2: c = P.y != Q.y ? (P.y < Q.y ? 1 : -1) : (P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0); break;
-        case 3: c = cmp_sum(P, Q, -1.0f); if (!c) c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0; break;
-        case 4: c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : (P.y != Q.y ? (P.y > Q.y ? 1 : -1) : 0); break;
-        case 5: c = cmp_sum(P, Q, 1.0f); if (!c) c = P.x != Q.x ? (P.x > Q.x ? 1 : -1) : 0; break;
-        case 6: c = P.y != Q.y ? (P.y > Q.y ? 1 : -1) : (P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0); break;
-        default: c = -cmp_sum(P, Q, -1.0f); if (!c) c = P.x != Q.x ? (P.x < Q.x ? 1 : -1) : 0; break;
-        }
-        if (c == 0) c = P.id < Q.id ? 1 : -1;  // coincident: the lowest index
-        return c > 0 ? 1 : 0;
-    }
-    __device__ __forceinline__ bool beats(const Ctx& c, int k, const Cand& P, const Cand& Q, Counters&) const
-    {
-        return beats_fast(c, k, P, Q) > 0;
-    }
-    __device__ __forceinline__ int place(const Ctx&, int, int, int) const { return 0; }
-    __device__ __forceinline__ void store(int, float, float, int) const {}
-    __device__ __forceinline__ void finalize(const Ctx&, int g, const Agg<NB>& a) const
+// One lane's extremes: its points come in increasing index order, so a
+// strict comparison keeps the lowest index among equal projections.
+struct ExtLane {
+    float v[8];
+    int id[8];
+    __device__ __forceinline__ void init()
     {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            gst(oct + 24 * g + 3 * k + 0, a.best[k].x);
-            gst(oct + 24 * g + 3 * k + 1, a.best[k].y);
-            gst(oct + 24 * g + 3 * k + 2, __int_as_float(a.best[k].id));
+        for (int k = 0; k < 8; ++k) {
+            v[k] = ext_is_max(k) ? -INFINITY : INFINITY;
+            id[k] = -1;
+        }
+    }
+    __device__ __forceinline__ void add(float x, float y, int q)
+    {
+        const float s = x + y, d = x - y;
+        const float pr[8] = {x, s, y, d, x, s, y, d};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool t = ext_is_max(k) ? (pr[k] > v[k]) : (pr[k] < v[k]);
+            v[k] = t ? pr[k] : v[k];
+            id[k] = t ? q : id[k];
         }
     }
 };
 
-// Stable compaction of one set's points outside the polygon. The polygon's
-// distinct corners come first in the subset (positions 0 .. nv-1), then the
-// kept points in input order: a coincident copy of a corner can then never
-// precede the corner, which holds the lowest index of its position. A point
-// is kept when the float32 filter finds it strictly right of an edge, or
-// cannot decide: keeping a point inside or on the polygon does not change
-// the hull, so no exact evaluation is needed here.
-struct PolKeep {
-    static constexpr int NB = 1;
-    static constexpr bool COUNTS = true, SCATTER = true, MULTI = false, MIDDLE = false;
-    static constexpr int ROWS = kRows;
-    // The corners in direction order; coincident neighbours give zero-length
-    // edges, which are skipped.
-    struct Ctx {
-        float vx[8], vy[8];
-        int vid[8];    // the corners' indices (they enter the subset once, first)
-        int base, nv;  // first read position; distinct corners
-    };
-    const float2* xy;
-    const int* gstart;
-    const float* oct;
-    float2* xy2;
-    int* ids2;
-    int* gs2;
-    int quad;  // 1: the four axis directions only
-    int G;
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
 
-    __device__ __forceinline__ int num_groups() const { return G; }
-    __device__ __forceinline__ int group_of(int q, int lo, int hi) const { return search_le(gstart, q, lo, hi); }
-    __device__ __forceinline__ int group_start(int g) const { return gld(gstart + g); }
-    __device__ __forceinline__ int group_end(int g) const { return gld(gstart + g + 1); }
-    __device__ __forceinline__ int corner_id(int g, int k) const
-    {
-        return __float_as_int(gld(oct + 24 * g + 3 * k + 2));
-    }
-    // corner k enters the subset: a direction in use whose corner no earlier
-    // direction in use has (the quadrilateral uses the even directions)
-    __device__ __forceinline__ static bool distinct(const int (&id)[8], int quad, int k)
-    {
-        if (quad && (k & 1)) return false;
-        bool dup = false;
+// The polygon's non-degenerate edges, wave-uniform (n = 0: all corners
+// coincide, every point is kept).
+//
+// Line test (|coordinates| <= 2^60): edge o -> o + (dx, dy) (dx, dy rounded)
+// as t = fma(nx, px, fma(ny, py, c)), nx = -dy, ny = dx, c = fl(fl(dy ox) -
+// fl(dx oy)). With D = |dx| My + |dy| Mx, where Mx, My bound |x|, |y| over
+// the input (the extremes in x and y), the rounding of the differences, of
+// c and of both fma's moves t from the exact orientation of (o, e, p) by at
+// most 9 u D (1 + 10 u) plus 5 * 2^-150 in the subnormal range (u = 2^-24),
+// so t > m = 2^-19 D + 2^-140 (32 u D) proves the orientation positive. The
+// bound on the coordinates keeps every term below 2^123 (no overflow).
+// Larger coordinates use the float32 orientation filter, whose overflow
+// gives an infinite or NaN bound and certifies nothing.
+constexpr float kLineCoordMax = 0x1p60f;
+constexpr float kLineRel = 0x1p-19f;
+
+struct KeepEdges {
+    float nx[8], ny[8], c[8], m[8];
+    int n;
+    bool line;  // the line test applies (else the orientation filter)
+};
+
+// edges in LDS for the orientation filter: ox, oy, dx, dy per edge
+struct KeepLds {
+    float e[4][8];
+};
+
+// corners cx, cy in direction order (the quadrilateral uses the even ones)
+__device__ __forceinline__ void keep_build(KeepEdges& E, KeepLds& L, const float (&cx)[8], const float (&cy)[8],
+                                           bool quad)
+{
+    const float Mx = fmaxf(fabsf(cx[0]), fabsf(cx[4]));  // min x, max x
+    const float My = fmaxf(fabsf(cy[2]), fabsf(cy[6]));  // min y, max y
+    E.line = fmaxf(Mx, My) <= kLineCoordMax;
+    E.n = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (j < k) dup = dup || ((!quad || !(j & 1)) && id[j] == id[k]);
-        return !dup;
-    }
-    __device__ __forceinline__ Ctx ctx(int g) const
-    {
-        Ctx c;
-        c.base = gld(gstart + g);
-        float ox[8], oy[8];
-        int oid[8];
+    for (int i = 0; i < 8; ++i) E.nx[i] = E.ny[i] = E.c[i] = E.m[i] = 0.0f;
+    const bool w0 = threadIdx.x == 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {  // independent loads, then register work
-            ox[k] = gld(oct + 24 * g + 3 * k);
-            oy[k] = gld(oct + 24 * g + 3 * k + 1);
-            oid[k] = __float_as_int(gld(oct + 24 * g + 3 * k + 2));
+    for (int i = 0; i < 8; ++i) {
+        if (quad && (i & 1)) continue;
+        const int j = quad ? ((i + 2) & 7) : ((i + 1) & 7);
+        if (cx[i] == cx[j] && cy[i] == cy[j]) continue;  // zero-length edge
+        const float dx = cx[j] - cx[i], dy = cy[j] - cy[i];
+        const float cc = dy * cx[i] - dx * cy[i];
+        const float mm = (fabsf(dx) * My + fabsf(dy) * Mx) * kLineRel + kFilterTau;
+        // (placed with selects so that the arrays stay in registers)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t == E.n) {
+                E.nx[t] = -dy;
+                E.ny[t] = dx;
+                E.c[t] = cc;
+                E.m[t] = mm;
+                if (w0) {
+                    L.e[0][t] = cx[i];
+                    L.e[1][t] = cy[i];
+                    L.e[2][t] = dx;
+                    L.e[3][t] = dy;
+                }
+            }
         }
-        c.nv = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            // the quadrilateral repeats each axis corner in the next direction
-            const int d = quad ? (k & ~1) : k;
-            c.vx[k] = ox[d];
-            c.vy[k] = oy[d];
-            c.vid[k] = oid[d];
-            c.nv += distinct(oid, quad, k) ? 1 : 0;
-        }
-        return c;
+        ++E.n;
     }
-    __device__ __forceinline__ void load(const Ctx& c, int, int q, float& x, float& y, int& id) const
-    {
-        const float2 v = gld(xy + q);
-        x = v.x; y = v.y; id = q - c.base;
-    }
-    __device__ __forceinline__ int classify(const Ctx& c, int, int q, float x, float y, int id, Cand& k, Counters& ctr) const
-    {
-        // subset size = corners + kept <= n: the corners are not kept again
-        bool corner = false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) corner = corner || id == c.vid[i];
-        bool keep = false;
+}
+
+// keep p: not certified strictly left of every edge
+__device__ __forceinline__ bool keep_point(const KeepEdges& E, const KeepLds& L, float px, float py, Counters& ctr)
+{
+    if (E.n == 0) return true;
+    bool in = true;
+    if (E.line) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int j = (i + 1) & 7;
-            if (c.vx[i] == c.vx[j] && c.vy[i] == c.vy[j]) continue;  // zero-length edge
-            const Orient32 o = orient32p(c.vx[i], c.vy[i], c.vx[j], c.vy[j], x, y);
-            ++ctr.orient;
-            keep = keep || !(o.d > o.es);  // not certainly left of the edge: outside, or undecided
+            if (i < E.n) in = in && fmaf(E.nx[i], px, fmaf(E.ny[i], py, E.c[i])) > E.m[i];
         }
-        k = no_cand();
-        return keep && !corner ? 0 : kNone;
-    }
-    __device__ __forceinline__ int beats_fast(const Ctx&, int, const Cand&, const Cand&) const { return 0; }
-    __device__ __forceinline__ bool beats(const Ctx&, int, const Cand&, const Cand&, Counters&) const { return false; }
-    __device__ __forceinline__ int place(const Ctx& c, int, int, int rank) const { return c.nv + rank; }
-    __device__ __forceinline__ void store(int dst, float x, float y, int id) const
-    {
-        gst(xy2 + dst, make_float2(x, y));
-        gst(ids2 + dst, id);
-    }
-    // the distinct corners, at positions 0 .. nv-1
-    __device__ __forceinline__ void write_corners(const Ctx& c) const
-    {
-        int n = 0;
+    } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (!distinct(c.vid, quad, k)) continue;
-            gst(xy2 + n, make_float2(c.vx[k], c.vy[k]));
-            gst(ids2 + n, c.vid[k]);
-            ++n;
+        for (int i = 0; i < 8; ++i) {
+            if (i < E.n) {
+                const float P = L.e[2][i] * (py - L.e[1][i]);
+                const float Q = L.e[3][i] * (px - L.e[0][i]);
+                const float d = P - Q;
+                const float es = (fabsf(P) + fabsf(Q)) * kFilterScale + kFilterTau;
+                in = in && d > es;
+            }
         }
     }
-    __device__ __forceinline__ void finalize(const Ctx& c, int, const Agg<NB>& a) const
-    {
-        write_corners(c);
-        gst(gs2 + 0, 0);
-        gst(gs2 + 1, c.nv + a.cnt[0]);
-    }
-};
+    ctr.orient += (uint32_t)E.n;
+    return !in;
+}
 
 // =========================================================== k_split ==
 template <bool IDS>
@@ -860,8 +809,7 @@ struct HullArgs {
     int* bad;                // G: new set had a non-finite coordinate
     // pre-filter (single hulls): 0 none, 1 quadrilateral, 2 octagon
     int prefilter;
-    float* oct;              // polygon corners: 8 x (x, y, index)
-    int* huge;               // a coordinate is outside the exact-sum range
+    uint64_t* ext;           // extreme keys: 8 per workgroup
     float2* xy2;             // the kept subset: points ...
     int* ids2;               // ... and their input indices
     int* gs2;                // {0, subset size}
@@ -1697,117 +1645,174 @@ done:
     flush_counters(a.stats, ctr);
 }
 
-// The kept points of one set, appended in any order (the subset's points
-// carry their input indices, so no tie rule depends on their order): each
-// workgroup streams one contiguous chunk, stages its kept points in LDS,
-// then reserves their places with one atomic add; a chunk with more kept
-// points than the stage holds streams again and writes them directly. The
-// corners go first (positions 0 .. nv-1); the subset's size goes to gs2[1]
-// and info->prefilter_n.
-constexpr int kKeepStage = 3072;
+// The pre-filter of a single hull (cooperative launch before k_hull, same
+// workspace). Each workgroup streams one contiguous chunk twice: first for
+// the eight extremes, whose keys go to ext (8 per workgroup) and, after a
+// grid barrier, are reduced by every workgroup; then to append the points
+// that the polygon does not certify inside to (xy2, ids2), in any order
+// (the subset's points carry their input indices, so no tie rule depends on
+// it). The kept points are staged in LDS and placed with one atomic add per
+// flush; the stage is flushed whenever the next block of rows could
+// overfill it. Leaves the subset's size in gs2[1] and info->prefilter_n (-1:
+// not run; a non-finite coordinate is left to k_hull's seed, which reports
+// it).
+constexpr int kPreRows = 8;                         // rows of loads in flight per wave (extremes)
+constexpr int kKeepRows = 4;                        // the same for the keep pass
+constexpr int kKeepStage = 2 * kBlock * kKeepRows;  // staged points per workgroup
 
-__device__ __forceinline__ void keep_append(const HullArgs& a, const PolKeep& pol, Counters& ctr)
+__device__ __forceinline__ float rfl_f(float v)
 {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_prefilter(HullArgs a)
+{
+    __shared__ uint64_t ext_w[kWaves][8];
+    __shared__ float corner_xy[2][8];
+    __shared__ KeepLds keep_lds;
     __shared__ float2 st_xy[kKeepStage];
     __shared__ int st_id[kKeepStage];
-    __shared__ int st_n, st_base, wcnt[kWaves];
+    __shared__ int st_n, st_base;
+    Counters ctr = {0u, 0u, 0u};
+    stamp(a, 0);
     const int nb = (int)gridDim.x, b = (int)blockIdx.x, lane = lane_id(), w = (int)(threadIdx.x >> 6);
-    const PolKeep::Ctx c = pol.ctx(0);
     const int P = a.N;
     const int CH = chunk_len(P, nb);
     const int cb = (int)min((long long)b * CH, (long long)P), ce = min(cb + CH, P);
     int wb, we;
     wave_part(cb, ce, w, wb, we);
-    if (threadIdx.x == 0) st_n = 0;
-    __syncthreads();
-    int mine = 0;  // kept points of this wave's part
-    for (int q0 = wb; q0 < we; q0 += 64) {
-        const int q = q0 + lane;
-        float x = 0.0f, y = 0.0f;
-        int id = 0;
-        bool keep = false;
-        if (q < we) {
-            Cand k;
-            pol.load(c, 0, q, x, y, id);
-            keep = pol.classify(c, 0, q, x, y, id, k, ctr) == 0;
-        }
-        const uint64_t M = __ballot(keep);
-        if (M) {
-            int off = 0;
-            if (lane == 0) off = atomicAdd(&st_n, (int)__popcll(M));
-            off = __shfl(off, 0);
-            const int r = off + __popcll(M & mask_lt(lane));
-            if (keep && r < kKeepStage) {
-                st_xy[r] = make_float2(x, y);
-                st_id[r] = id;
+    // every wave's part has at most this many blocks of kKeepRows rows
+    const int iters = (((ce - cb + 63) / 64 + kWaves - 1) / kWaves + kKeepRows - 1) / kKeepRows;
+
+    // ---- extremes of this wave's part, then of the workgroup's chunk
+    {
+        ExtLane L;
+        L.init();
+        bool bad = false;
+        for (int q0 = wb; q0 < we; q0 += 64 * kPreRows) {
+            float2 v[kPreRows];
+#pragma unroll
+            for (int r = 0; r < kPreRows; ++r) {
+                const int q = q0 + 64 * r + lane;
+                v[r] = q < we ? gld(a.xy + q) : make_float2(0.0f, 0.0f);
             }
-            mine += __popcll(M);
+#pragma unroll
+            for (int r = 0; r < kPreRows; ++r) {
+                const int q = q0 + 64 * r + lane;
+                if (q < we) {
+                    bad = bad || !(isfinite(v[r].x) && isfinite(v[r].y));
+                    L.add(v[r].x, v[r].y, q);
+                }
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(a.err, kErrNonFinite);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint64_t v = ext_key(k, L.v[k], L.id[k]);
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v = ext_pick(k, v, shfl_xor_u64(v, m));
+            if (lane == 0) ext_w[w][k] = v;
         }
     }
-    if (lane == 0) wcnt[w] = mine;
     __syncthreads();
-    const int n = st_n;
-    if (threadIdx.x == 0) st_base = n > 0 ? atomicAdd(&a.info->keep_n, n) : 0;
-    __syncthreads();
-    const int base = c.nv + st_base;
-    if (n <= kKeepStage) {
-        for (int i = (int)threadIdx.x; i < n; i += kBlock) {
-            gst(a.xy2 + base + i, st_xy[i]);
-            gst(a.ids2 + base + i, st_id[i]);
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint64_t v = lane < kWaves ? ext_w[lane][k] : ext_none(k);
+#pragma unroll
+            for (int m = kWaves / 2; m >= 1; m >>= 1) v = ext_pick(k, v, shfl_xor_u64(v, m));
+            if (lane == 0) gst(a.ext + 8 * b + k, v);
         }
-    } else {
-        // too many for the stage: stream the chunk again, in wave order
-        int r = base;
-        for (int v = 0; v < w; ++v) r += wcnt[v];
-        for (int q0 = wb; q0 < we; q0 += 64) {
-            const int q = q0 + lane;
-            float x = 0.0f, y = 0.0f;
-            int id = 0;
-            bool keep = false;
-            if (q < we) {
-                Cand k;
-                pol.load(c, 0, q, x, y, id);
-                keep = pol.classify(c, 0, q, x, y, id, k, ctr) == 0;
+    }
+    grid_sync(a.bar, a.err);
+    if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;  // (the same for every workgroup)
+
+    // ---- the corners: every workgroup reduces the keys of all workgroups
+    if (w < 4) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint64_t v = ext_none(k);
+            for (int t = (int)threadIdx.x; t < nb; t += 256) v = ext_pick(k, v, gld(a.ext + 8 * t + k));
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v = ext_pick(k, v, shfl_xor_u64(v, m));
+            if (lane == 0) ext_w[w][k] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = (int)threadIdx.x;
+        uint64_t v = ext_w[0][k];
+#pragma unroll
+        for (int t = 1; t < 4; ++t) v = ext_pick(k, v, ext_w[t][k]);
+        const float2 c = gld(a.xy + ext_index(k, v));  // N > 0: every direction has a point
+        corner_xy[0][k] = c.x;
+        corner_xy[1][k] = c.y;
+    }
+    if (threadIdx.x == 0) st_n = 0;
+    __syncthreads();
+    {
+        float cx[8], cy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            cx[k] = rfl_f(corner_xy[0][k]);
+            cy[k] = rfl_f(corner_xy[1][k]);
+        }
+        KeepEdges E;
+        keep_build(E, keep_lds, cx, cy, a.prefilter == 1);
+        __syncthreads();  // keep_lds
+
+        // ---- the points not certified inside, staged per workgroup
+        for (int it = 0; it < iters; ++it) {
+            const int q0 = wb + it * 64 * kKeepRows;
+            float2 v[kKeepRows];
+#pragma unroll
+            for (int r = 0; r < kKeepRows; ++r) {
+                const int q = q0 + 64 * r + lane;
+                v[r] = q < we ? gld(a.xy + q) : make_float2(0.0f, 0.0f);
             }
-            const uint64_t M = __ballot(keep);
-            if (keep) {
-                const int dst = r + __popcll(M & mask_lt(lane));
-                gst(a.xy2 + dst, make_float2(x, y));
-                gst(a.ids2 + dst, id);
+#pragma unroll
+            for (int r = 0; r < kKeepRows; ++r) {
+                const int q = q0 + 64 * r + lane;
+                const bool kp = q < we && keep_point(E, keep_lds, v[r].x, v[r].y, ctr);
+                const uint64_t M = __ballot(kp);
+                if (M) {
+                    int off = 0;
+                    if (lane == 0) off = atomicAdd(&st_n, (int)__popcll(M));
+                    off = __shfl(off, 0);
+                    if (kp) {
+                        const int rr = off + __popcll(M & mask_lt(lane));
+                        st_xy[rr] = v[r];
+                        st_id[rr] = q;
+                    }
+                }
             }
-            r += __popcll(M);
+            __syncthreads();
+            const int n = st_n;
+            __syncthreads();  // every wave has read n before the next appends
+            // flush when the next block of rows (at most kBlock * kKeepRows
+            // points) might not fit, and at the end
+            if (n > kKeepStage - kBlock * kKeepRows || (it == iters - 1 && n > 0)) {
+                if (threadIdx.x == 0) st_base = atomicAdd(&a.info->keep_n, n);
+                __syncthreads();
+                const int base = st_base;
+                for (int i = (int)threadIdx.x; i < n; i += kBlock) {
+                    gst(a.xy2 + base + i, st_xy[i]);
+                    gst(a.ids2 + base + i, st_id[i]);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) st_n = 0;
+                __syncthreads();
+            }
         }
     }
     grid_sync(a.bar, a.err);
     if (b == 0 && threadIdx.x == 0) {
-        pol.write_corners(c);
-        const int total = c.nv + ld_flag(&a.info->keep_n);
+        const int total = ld_flag(&a.info->keep_n);
         a.gs2[0] = 0;
         a.gs2[1] = total;
         a.info->prefilter_n = total;
     }
-}
-
-// The pre-filter of a single hull (cooperative launch before k_hull, same
-// workspace): the extreme points in eight directions, then the stable
-// compaction of the points outside their polygon into (xy2, ids2). Leaves
-// the subset's size in info->prefilter_n (-1: not run, the coordinates are
-// outside the exact-sum range; a non-finite coordinate is left to k_hull's
-// seed, which reports it).
-__global__ __launch_bounds__(kBlock) void k_prefilter(HullArgs a)
-{
-    __shared__ ChunkShared<PolExt8> sh;
-    __shared__ Pair red[kWaves];
-    Counters ctr = {0u, 0u, 0u};
-    stamp(a, 0);
-    {
-        PolExt8 pol{a.xy, a.gstart, a.oct, a.err, a.huge, a.G};
-        phase_reduce(a, pol, a.N, sh, red, ctr);
-    }
-    if (!(ld_flag(a.err) & (kErrNonFinite | kErrBounds)) && !ld_flag(a.huge)) {
-        PolKeep pol{a.xy, a.gstart, a.oct, a.xy2, a.ids2, a.gs2, a.prefilter == 1 ? 1 : 0, a.G};
-        keep_append(a, pol, ctr);
-    }
+done:
     stamp(a, 5);
     flush_counters(a.stats, ctr);
 }
@@ -1832,7 +1837,6 @@ __global__ void k_reset(HullArgs a)
         a.info->pass_traced = 0;
         a.info->prefilter_n = -1;
         a.info->keep_n = 0;
-        if (a.huge) *a.huge = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;

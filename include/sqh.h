@@ -63,6 +63,10 @@ extern "C" {
 #define SQH_PREFILTER_QUAD    1  /* the paper's first mode: extremes in x and y */
 #define SQH_PREFILTER_OCTAGON 2  /* also the extremes of x + y and x - y */
 
+/* Data layout of the passes of single hulls (sqh_set_variant). */
+#define SQH_VARIANT_PARTITION 0  /* each pass partitions a segment into its children */
+#define SQH_VARIANT_SORTED    1  /* the paper's x-sorted chains: sort once, then only remove */
+
 typedef struct sqh_ctx sqh_ctx;
 
 #define SQH_MAX_TIMED_PASSES 64
@@ -90,6 +94,9 @@ typedef struct sqh_stats {
     int64_t pass_points[SQH_MAX_TIMED_PASSES];    /* points entering pass k */
     int64_t pass_segments[SQH_MAX_TIMED_PASSES];  /* segments in pass k */
     double  pass_ms[SQH_MAX_TIMED_PASSES];        /* kernel time of pass k */
+    double  ms_sort;          /* sorted-chain variant: the sort of the first segments */
+    int64_t sorted_points;    /* sorted-chain variant: points sorted; -1: no sort ran */
+    int64_t sort_violations;  /* sorted-chain variant: neighbours found out of order after the sort (0) */
 } sqh_stats;
 
 /*
@@ -108,18 +115,32 @@ void sqh_destroy(sqh_ctx *ctx);
 int sqh_set_precision(sqh_ctx *ctx, int mode);
 
 /*
- * Pre-filter for sqh_hull (batched calls and the engine ignore it): the
- * paper's first mode (section 4.2, Table 2's Mode 1) finds the extreme
- * points in x and y and discards the points inside their quadrilateral
- * before the first split; SQH_PREFILTER_OCTAGON adds the extremes of x + y
- * and x - y. Each extreme is a hull vertex (ties: see the kernels), the
- * points strictly outside the polygon are compacted stably and the method
- * runs on them plus the corners. The output is identical to the plain
- * method. Inputs with a coordinate above 2^125 in magnitude (where x + y
- * could overflow float32 and the exact comparison of sums fails) run the
- * plain method. Returns SQH_OK or SQH_EINVAL.
+ * Pre-filter for calls on one set (sqh_hull, or a batch of one set; the
+ * engine ignores it): the paper's first mode (section 4.2, Table 2's
+ * Mode 1) takes extreme points in x and y and discards the points inside
+ * their quadrilateral before the first split; SQH_PREFILTER_OCTAGON adds
+ * the extremes of x + y and x - y (rounded to float32). The corners are
+ * input points; a point is discarded only when a float32 test certifies it
+ * strictly inside every edge of their polygon, which makes it an interior
+ * point of the hull. The method then runs on the remaining points, in an
+ * unspecified order, carrying their input indices, so the output is
+ * identical to the plain method's. Returns SQH_OK or SQH_EINVAL.
  */
 int sqh_set_prefilter(sqh_ctx *ctx, int mode);
+
+/*
+ * Layout of the passes for calls on one set (sqh_hull, or a batch of one
+ * set; other batches and the engine ignore it). SQH_VARIANT_PARTITION
+ * (default): every pass moves each segment's points into its two children
+ * (a stable three-way partition). SQH_VARIANT_SORTED: the paper's layout
+ * (sections 3, 4.3 and 4.4): after the first split the points of each
+ * first segment are sorted by x, ascending on the lower chain and
+ * descending on the upper one, with a radix sort; every later pass then
+ * only removes points, the children staying in order. The output is
+ * identical; the stats report the sort's time, the points sorted and a
+ * check of the order (sort_violations, 0). Returns SQH_OK or SQH_EINVAL.
+ */
+int sqh_set_variant(sqh_ctx *ctx, int variant);
 
 /*
  * Device workspace, in bytes, needed by sqh_hull (n_sets = 1) or

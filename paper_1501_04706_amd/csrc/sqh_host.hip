@@ -31,7 +31,7 @@ struct Layout {
     size_t x[2], y[2], id[2];
     size_t gstart, sets, recs, rec_cid, segs[2], seg_cid[2], vstart[2];
     size_t bitmap, vidx, vlist, wprefix, slots, ctab, bar, err, stats, sv, info;
-    size_t ext, xy2, ids2, gs2;
+    size_t ext, xy2, ids2, gs2, shist, stot;
     int64_t vcap;
     size_t bytes;
 };
@@ -81,6 +81,9 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     L.xy2 = take(sizeof(float2) * (size_t)std::max<int64_t>(N, 1));
     L.ids2 = take(sizeof(int) * (size_t)std::max<int64_t>(N, 1));
     L.gs2 = take(sizeof(int) * 2);
+    // sorted-chain variant: bucket counts per workgroup and totals
+    L.shist = take(sizeof(int) * (size_t)kSortBuckets * (size_t)kMaxGrid);
+    L.stot = take(sizeof(int) * (size_t)kSortBuckets);
     L.bytes = o;
     return true;
 }
@@ -109,6 +112,7 @@ struct sqh_ctx {
     int ntune = 0;
     int engine_grid = 0;  // workgroups of an engine step (0: all but 1/8 of the co-resident ones)
     int prefilter = 0;    // SQH_PREFILTER_*
+    int variant = 0;      // SQH_VARIANT_*
 };
 
 struct sqh_graph {
@@ -205,6 +209,9 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.timing = ctx->trace == 1 ? 2 : (ctx->trace == 2 ? 3 : 1);
     a.tail_points = tu.tail;
     a.prefilter = nsets == 1 ? ctx->prefilter : 0;
+    a.sorted = nsets == 1 && ctx->variant == SQH_VARIANT_SORTED ? 1 : 0;
+    a.shist = static_cast<int*>(at(L.shist));
+    a.stot = static_cast<int*>(at(L.stot));
     a.ext = static_cast<uint64_t*>(at(L.ext));
     a.xy2 = static_cast<float2*>(at(L.xy2));
     a.ids2 = static_cast<int*>(at(L.ids2));
@@ -214,15 +221,27 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     return SQH_OK;
 }
 
-// The persistent kernel for these arguments: the instance that reads the
-// pre-filter's subset only where the pre-filter runs.
+// The cooperative launches of one call after the workspace reset: the
+// pre-filter where it runs, then the persistent kernel (the instance that
+// reads the pre-filter's subset only where the pre-filter runs), or for the
+// sorted-chain variant its first phases, k_sort and its passes.
 inline bool pre_runs(const HullArgs& a) { return a.prefilter && a.G == 1 && a.N > 0; }
-inline const void* hull_kernel(const HullArgs& a)
+inline int coop_launches(const HullArgs& a, const void* (&f)[4])
 {
-    return pre_runs(a) ? reinterpret_cast<const void*>(k_hull<true>) : reinterpret_cast<const void*>(k_hull<false>);
+    int n = 0;
+    if (pre_runs(a)) f[n++] = reinterpret_cast<const void*>(k_prefilter);
+    if (a.sorted && a.G == 1) {
+        f[n++] = reinterpret_cast<const void*>(k_hull<kHullFirst>);
+        f[n++] = reinterpret_cast<const void*>(k_sort);
+        f[n++] = reinterpret_cast<const void*>(k_hull<kHullPasses>);
+    } else {
+        f[n++] = pre_runs(a) ? reinterpret_cast<const void*>(k_hull<kHullPre>)
+                             : reinterpret_cast<const void*>(k_hull<kHullPlain>);
+    }
+    return n;
 }
 
-// Enqueue the workspace reset and the persistent kernel, bracketed by events.
+// Enqueue the workspace reset and the cooperative launches, bracketed by events.
 int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
 {
     HIP_OK(hipEventRecord(ctx->ev0, st));
@@ -230,10 +249,9 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
-    if (pre_runs(a))
-        HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_prefilter), dim3(grid), dim3(kBlock), argv,
-                                          0, st));
-    HIP_OK(hipLaunchCooperativeKernel(hull_kernel(a), dim3(grid), dim3(kBlock), argv, 0, st));
+    const void* f[4];
+    const int nf = coop_launches(a, f);
+    for (int i = 0; i < nf; ++i) HIP_OK(hipLaunchCooperativeKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
 }
@@ -275,6 +293,8 @@ int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t
     const int64_t h = hi.h_total;
     S.hull_size = h;
     S.prefilter_points = hi.prefilter_n;
+    S.sorted_points = hi.sort_n;
+    S.sort_violations = hi.sort_bad;
     if (timed) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
@@ -296,6 +316,7 @@ void phase_times(const HullInfo& hi, sqh_stats& S)
     for (int i = 1; i < hi.nstamps && i < kMaxStamps; ++i) {
         const int tag = hi.stamp_tag[i];
         if (tag == 5) S.ms_prefilter += dt(i);
+        else if (tag == 6) S.ms_sort += dt(i);
         else if (tag == 1) S.ms_seed += dt(i);
         else if (tag == 2) S.ms_split += dt(i);
         else if (tag == 3) S.ms_first += dt(i);
@@ -509,16 +530,24 @@ int sqh_create(sqh_ctx** out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return SQH_EDEVICE; }
     c->cus = prop.multiProcessorCount;
-    int per_cu = 0, per_cu_pre = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_hull<false>), kBlock,
-                                                     0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pre, reinterpret_cast<const void*>(k_hull<true>), kBlock,
-                                                     0) != hipSuccess ||
-        std::min(per_cu, per_cu_pre) < 1) {
+    // co-resident workgroups: the smallest over every cooperative kernel
+    int per_cu = 1 << 30;
+    {
+        const void* coop[] = {reinterpret_cast<const void*>(k_hull<kHullPlain>),
+                              reinterpret_cast<const void*>(k_hull<kHullPre>),
+                              reinterpret_cast<const void*>(k_hull<kHullFirst>),
+                              reinterpret_cast<const void*>(k_hull<kHullPasses>),
+                              reinterpret_cast<const void*>(k_prefilter), reinterpret_cast<const void*>(k_sort)};
+        for (const void* f : coop) {
+            int k = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, kBlock, 0) != hipSuccess) k = 0;
+            per_cu = std::min(per_cu, k);
+        }
+    }
+    if (per_cu < 1) {
         delete c;
         return SQH_EDEVICE;
     }
-    per_cu = std::min(per_cu, per_cu_pre);
     c->max_grid = std::min(kMaxGrid, per_cu * c->cus);
     {
         const char* t = getenv("SQH_TRACE");
@@ -553,6 +582,13 @@ int sqh_set_prefilter(sqh_ctx* c, int mode)
 {
     if (!c || mode < SQH_PREFILTER_NONE || mode > SQH_PREFILTER_OCTAGON) return SQH_EINVAL;
     c->prefilter = mode;
+    return SQH_OK;
+}
+
+int sqh_set_variant(sqh_ctx* c, int variant)
+{
+    if (!c || (variant != SQH_VARIANT_PARTITION && variant != SQH_VARIANT_SORTED)) return SQH_EINVAL;
+    c->variant = variant;
     return SQH_OK;
 }
 
@@ -707,9 +743,9 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
         delete g;
         return rc;
     }
-    // two kernel nodes: the workspace reset, then the persistent kernel,
-    // marked cooperative so that every workgroup is resident at once
-    hipGraphNode_t n_reset = nullptr, n_pre = nullptr, n_hull = nullptr;
+    // a chain of kernel nodes: the workspace reset, then the cooperative
+    // launches of the call, each marked cooperative so that every
+    // workgroup is resident at once
     void* argv[] = {static_cast<void*>(&g->args)};
     hipKernelNodeParams kp{};
     kp.func = reinterpret_cast<void*>(k_reset);
@@ -718,23 +754,24 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     kp.sharedMemBytes = 0;
     kp.kernelParams = argv;
     kp.extra = nullptr;
-    hipKernelNodeParams hp = kp;
-    hp.func = const_cast<void*>(hull_kernel(g->args));
-    hp.gridDim = dim3(tu.grid);
-    hp.blockDim = dim3(kBlock);
-    hipKernelNodeParams pp = hp;
-    pp.func = reinterpret_cast<void*>(k_prefilter);
-    const bool pre = pre_runs(g->args);
     hipKernelNodeAttrValue coop{};
     coop.cooperative = 1;
+    hipGraphNode_t prev = nullptr;
     bool ok = hipGraphCreate(&g->graph, 0) == hipSuccess &&
-              hipGraphAddKernelNode(&n_reset, g->graph, nullptr, 0, &kp) == hipSuccess;
-    if (ok && pre)
-        ok = hipGraphAddKernelNode(&n_pre, g->graph, &n_reset, 1, &pp) == hipSuccess &&
-             hipGraphKernelNodeSetAttribute(n_pre, hipKernelNodeAttributeCooperative, &coop) == hipSuccess;
-    ok = ok && hipGraphAddKernelNode(&n_hull, g->graph, pre ? &n_pre : &n_reset, 1, &hp) == hipSuccess &&
-         hipGraphKernelNodeSetAttribute(n_hull, hipKernelNodeAttributeCooperative, &coop) == hipSuccess &&
-         hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+              hipGraphAddKernelNode(&prev, g->graph, nullptr, 0, &kp) == hipSuccess;
+    const void* f[4];
+    const int nf = coop_launches(g->args, f);
+    for (int i = 0; ok && i < nf; ++i) {
+        hipKernelNodeParams hp = kp;
+        hp.func = const_cast<void*>(f[i]);
+        hp.gridDim = dim3(tu.grid);
+        hp.blockDim = dim3(kBlock);
+        hipGraphNode_t node = nullptr;
+        ok = hipGraphAddKernelNode(&node, g->graph, &prev, 1, &hp) == hipSuccess &&
+             hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &coop) == hipSuccess;
+        prev = node;
+    }
+    ok = ok && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
     if (!ok) {
         sqh_graph_destroy(g);
         return SQH_EDEVICE;

@@ -755,6 +755,8 @@ struct HullInfo {
     int pass_traced;  // timing 3: the first grid pass has been traced
     int prefilter_n;  // points kept by the pre-filter (+ corners), -1 if it did not run
     int keep_n;       // pre-filter: kept points appended so far
+    int sort_n;       // sorted-chain variant: points sorted (-1: no sort)
+    int sort_bad;     // sorted-chain variant: neighbours out of order after the sort
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -813,6 +815,11 @@ struct HullArgs {
     float2* xy2;             // the kept subset: points ...
     int* ids2;               // ... and their input indices
     int* gs2;                // {0, subset size}
+    // sorted-chain variant (single hulls; the host launches k_sort between
+    // the first phases and the passes)
+    int sorted;
+    int* shist;              // kSortBuckets x workgroups
+    int* stot;               // kSortBuckets
 };
 
 
@@ -1517,11 +1524,20 @@ __device__ __forceinline__ void tail_passes(const HullArgs& a, int cur, int pass
     }
 }
 
-// PRE: the launch follows k_prefilter and may run on its subset (a launch
-// without the pre-filter is built without the subset's index loads).
-template <bool PRE>
+// The persistent kernel's instances:
+//   kHullPlain  the whole hull, no pre-filter (built without the subset's
+//               index loads)
+//   kHullPre    the whole hull after k_prefilter, on its subset if it ran
+//   kHullFirst  the first phases only (seed, first split, first
+//               compaction), after which k_sort orders the segments
+//   kHullPasses the passes and the emission only, after k_sort
+// The last three may follow k_prefilter.
+constexpr int kHullPlain = 0, kHullPre = 1, kHullFirst = 2, kHullPasses = 3;
+
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
 {
+    constexpr bool PRE = MODE != kHullPlain;
     __shared__ ChunkShared<PolFirst> sh_first;
     __shared__ Pair red[kWaves];
     // the vertex list of the one-workgroup emission and the LDS of the last
@@ -1556,7 +1572,12 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     if (ld_flag(a.err) & kErrBounds) goto done;  // set offsets rejected by k_reset
     // A single hull of few points runs on workgroup 0 alone (no grid
     // barriers); the other workgroups wait for its emission decision.
-    if (a.G == 1 && in_n <= kSmallInput) {
+    if (MODE == kHullPasses) {
+        // the first phases ran in an earlier launch; a rejected input ended there
+        if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;
+        goto passes;
+    }
+    if (MODE != kHullFirst && a.G == 1 && in_n <= kSmallInput) {
         tail = true;
         if (b == 0) {
             if constexpr (PRE)
@@ -1579,7 +1600,8 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
                      : first_phases<false, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
         else
             ok = first_phases<false, false>(a, in_xy, in_gstart, in_ids, in_n, sh_first, red, ctr);
-        if (!ok) goto done;
+        if (!ok || MODE == kHullFirst) goto done;
+    passes:
         // ---- segmented passes over all segments of all sets
         for (;; ++pass) {
             const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
@@ -1817,6 +1839,200 @@ done:
     flush_counters(a.stats, ctr);
 }
 
+// ---- the sorted-chain variant ------------------------------------------
+//
+// The paper sorts the points below and above the first split line by x
+// (sections 3 and 4.3) and afterwards only removes points: a segment is a
+// run of consecutive points between two hull vertices (section 4.4). Here
+// the first compaction's segments (at most four for one set) are sorted by
+// x after the first phases: ascending where the segment runs left to right
+// (A.x <= B.x, the lower chain), descending where it runs right to left.
+// Every later pass partitions each segment stably into its two children,
+// and on an x-sorted segment the points outside (A, C) all precede C and
+// those outside (C, B) all follow it, so the children come out in order and
+// the pass only removes points; the hull is the same.
+//
+// k_sort (cooperative): an LSD radix sort of 8-bit digits over the
+// order-preserving image of x (complemented on right-to-left segments),
+// stable in every pass; every pass also takes the segment index as its top
+// two bits, so that no point leaves its segment's range. Each pass:
+// per-wave bucket counts in LDS -> per-workgroup counts (with per-wave
+// prefixes kept in LDS) -> grid barrier -> exclusive scan of each bucket
+// over the workgroups -> grid barrier -> bucket bases -> a stable scatter
+// in which the lanes of one row take their ranks from ballots over the
+// bucket bits. Four passes take the points from buffer 0 through buffer 1
+// and back. Afterwards neighbours in a segment are checked (info->sort_bad
+// counts pairs out of order; 0 expected).
+constexpr int kSortSegs = 4;        // segments after the first compaction of one set
+constexpr int kSortBuckets = 1024;  // 2 segment bits + 8 digit bits
+
+// the segment of position q: vs[k] is segment k's first position (vs[S..4] = V)
+__device__ __forceinline__ int sort_seg(int q, const int (&vs)[kSortSegs + 1])
+{
+    return (q >= vs[1] ? 1 : 0) + (q >= vs[2] ? 1 : 0) + (q >= vs[3] ? 1 : 0);
+}
+
+// The points of segment k occupy its slots off[k] .. off[k] + len - 1 (the
+// slot ranges leave gaps for vertices); positions number them densely. The
+// sort runs over positions and reads and writes the matching slots.
+__device__ __forceinline__ int sort_slot(int q, int sg, const int (&vs)[kSortSegs + 1], const int (&off)[kSortSegs])
+{
+    return off[sg] + (q - vs[sg]);
+}
+
+__device__ __forceinline__ uint32_t sort_key(float x, int s, uint32_t desc)
+{
+    const uint32_t o = ord32(x + 0.0f);  // -0 -> +0
+    return ((desc >> s) & 1u) ? ~o : o;
+}
+
+// lanes of this wave whose bucket equals this lane's (among valid lanes)
+__device__ __forceinline__ uint64_t sort_match(int bucket, bool valid, int nbits)
+{
+    uint64_t m = __ballot(valid);
+    for (int i = 0; i < nbits; ++i) {
+        const bool bit = (bucket >> i) & 1;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort(HullArgs a)
+{
+    __shared__ int wtab[kWaves][kSortBuckets];  // per-wave counts, then write offsets
+    __shared__ Pair red[kWaves];
+    __shared__ int sbad;
+    Counters ctr = {0u, 0u, 0u};
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x, lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const int t = (int)threadIdx.x;
+    stamp(a, 0);
+    int S = 0, V = 0;
+    if (!(ld_flag(a.err) & (kErrNonFinite | kErrBounds))) {
+        S = ld_flag(a.sv);
+        V = ld_flag(a.sv + 1);
+    }
+    if (S > 0 && S <= kSortSegs && V > 0) {
+        int vs[kSortSegs + 1], off[kSortSegs];
+        uint32_t desc = 0;
+#pragma unroll
+        for (int k = 0; k <= kSortSegs; ++k) vs[k] = k <= S ? gld(a.vstart[0] + k) : V;
+#pragma unroll
+        for (int k = 0; k < kSortSegs; ++k) {
+            off[k] = 0;
+            if (k < S) {
+                const Seg g = gld(a.segs[0] + k);
+                desc |= (g.ax > g.bx ? 1u : 0u) << k;
+                off[k] = g.off;
+            }
+        }
+        const int CH = chunk_len(V, nb);
+        const int cb = (int)min((long long)b * CH, (long long)V), ce = min(cb + CH, V);
+        int wb, we;
+        wave_part(cb, ce, w, wb, we);
+        for (int ps = 0; ps < 4; ++ps) {
+            const int src = ps & 1, dst = src ^ 1;
+            const int shift = 8 * ps;
+            constexpr int nbits = 10, nbk = kSortBuckets;
+            // 1. per-wave counts of this wave's part
+            for (int i = t; i < kWaves * nbk; i += kBlock) wtab[i / nbk][i % nbk] = 0;
+            __syncthreads();
+            for (int q0 = wb; q0 < we; q0 += 64) {
+                const int q = q0 + lane;
+                const bool valid = q < we;
+                int bucket = 0;
+                if (valid) {
+                    const int sg = sort_seg(q, vs);
+                    bucket = (int)((sort_key(gld(a.X[src] + sort_slot(q, sg, vs, off)), sg, desc) >> shift) & 255u);
+                    bucket |= sg << 8;
+                }
+                const uint64_t m = sort_match(bucket, valid, nbits);
+                if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);  // the group's last lane
+            }
+            __syncthreads();
+            // 2. per bucket: prefixes over the waves (kept), the workgroup's count
+            for (int j = t; j < nbk; j += kBlock) {
+                int run = 0;
+#pragma unroll
+                for (int v = 0; v < kWaves; ++v) {
+                    const int c = wtab[v][j];
+                    wtab[v][j] = run;
+                    run += c;
+                }
+                gst(a.shist + j * nb + b, run);
+            }
+            grid_sync(a.bar, a.err);
+            // 3. per bucket: exclusive scan over the workgroups, and the total
+            for (int j = b; j < nbk; j += nb) {
+                const int c = t < nb ? gld(a.shist + j * nb + t) : 0;
+                Pair tot;
+                const Pair ex = block_excl_scan(Pair{c, 0}, red, &tot);
+                if (t < nb) gst(a.shist + j * nb + t, ex.a);
+                if (t == 0) gst(a.stot + j, tot.a);
+                __syncthreads();
+            }
+            grid_sync(a.bar, a.err);
+            // 4. bucket bases (every workgroup), then this wave's write offsets
+            {
+                const int c = t < nbk ? gld(a.stot + t) : 0;
+                Pair tot;
+                const Pair ex = block_excl_scan(Pair{c, 0}, red, &tot);
+                const int mine = t < nbk ? ex.a + gld(a.shist + t * nb + b) : 0;
+                __syncthreads();
+                if (t < nbk) {
+#pragma unroll
+                    for (int v = 0; v < kWaves; ++v) wtab[v][t] += mine;
+                }
+                __syncthreads();
+            }
+            // 5. stable scatter, row by row
+            for (int q0 = wb; q0 < we; q0 += 64) {
+                const int q = q0 + lane;
+                const bool valid = q < we;
+                float x = 0.0f, y = 0.0f;
+                int id = 0, bucket = 0;
+                if (valid) {
+                    const int sg = sort_seg(q, vs);
+                    const int sl = sort_slot(q, sg, vs, off);
+                    x = gld(a.X[src] + sl);
+                    y = gld(a.Y[src] + sl);
+                    id = gld(a.I[src] + sl);
+                    bucket = (int)((sort_key(x, sg, desc) >> shift) & 255u);
+                    bucket |= sg << 8;
+                }
+                const uint64_t m = sort_match(bucket, valid, nbits);
+                int pos = 0;
+                if (valid) pos = wtab[w][bucket] + __popcll(m & mask_lt(lane));
+                if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);
+                if (valid) {
+                    const int dl = sort_slot(pos, sort_seg(pos, vs), vs, off);
+                    gst(a.X[dst] + dl, x);
+                    gst(a.Y[dst] + dl, y);
+                    gst(a.I[dst] + dl, id);
+                }
+            }
+            grid_sync(a.bar, a.err);
+        }
+        // 6. check: neighbours inside a segment in key order
+        if (t == 0) sbad = 0;
+        __syncthreads();
+        int bad = 0;
+        for (int q = cb + t; q < ce; q += kBlock) {
+            if (q == 0) continue;
+            const int sg = sort_seg(q, vs);
+            if (sort_seg(q - 1, vs) != sg) continue;
+            const int sl = sort_slot(q, sg, vs, off);  // (q - 1 is the slot before)
+            if (sort_key(gld(a.X[0] + sl), sg, desc) < sort_key(gld(a.X[0] + sl - 1), sg, desc)) ++bad;
+        }
+        if (bad) atomicAdd(&sbad, bad);
+        __syncthreads();
+        if (t == 0 && sbad) atomicAdd(&a.info->sort_bad, sbad);
+        if (b == 0 && t == 0) a.info->sort_n = V;
+    }
+    stamp(a, 6);
+    flush_counters(a.stats, ctr);
+}
+
 // Per-call initialisation (a normal launch before k_hull): barrier state,
 // error word, counters, info block, the vertex bitmap, the first child
 // records, and the set starts (validated).
@@ -1837,6 +2053,8 @@ __global__ void k_reset(HullArgs a)
         a.info->pass_traced = 0;
         a.info->prefilter_n = -1;
         a.info->keep_n = 0;
+        a.info->sort_n = -1;
+        a.info->sort_bad = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;

@@ -28,6 +28,8 @@ SQH_ENOTFOUND = -6
 SQH_PREFILTER_NONE = 0
 SQH_PREFILTER_QUAD = 1
 SQH_PREFILTER_OCTAGON = 2
+SQH_VARIANT_PARTITION = 0
+SQH_VARIANT_SORTED = 1
 SQH_FP32_FILTER = 0
 SQH_FP64_ONLY = 1
 
@@ -71,6 +73,9 @@ class SqhStats(ctypes.Structure):
         ("pass_points", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
         ("pass_segments", ctypes.c_int64 * SQH_MAX_TIMED_PASSES),
         ("pass_ms", ctypes.c_double * SQH_MAX_TIMED_PASSES),
+        ("ms_sort", ctypes.c_double),
+        ("sorted_points", ctypes.c_int64),
+        ("sort_violations", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -100,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.sqh_set_precision.restype = c_int
     lib.sqh_set_prefilter.argtypes = [vp, c_int]
     lib.sqh_set_prefilter.restype = c_int
+    lib.sqh_set_variant.argtypes = [vp, c_int]
+    lib.sqh_set_variant.restype = c_int
     lib.sqh_workspace_bytes.argtypes = [i64, i64]
     lib.sqh_workspace_bytes.restype = ctypes.c_size_t
     lib.sqh_hull.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
@@ -181,6 +188,10 @@ def sqh_set_precision(ctx: int, mode: int) -> int:
 
 def sqh_set_prefilter(ctx: int, mode: int) -> int:
     return load().sqh_set_prefilter(ctx, mode)
+
+
+def sqh_set_variant(ctx: int, variant: int) -> int:
+    return load().sqh_set_variant(ctx, variant)
 
 
 def sqh_workspace_bytes(n_total: int, n_sets: int = 1) -> int:
@@ -353,6 +364,11 @@ class Hull:
         rc = sqh_set_prefilter(self.ctx, mode)
         if rc != SQH_OK:
             raise SqhError(rc, "sqh_set_prefilter")
+
+    def set_variant(self, variant: int):
+        rc = sqh_set_variant(self.ctx, variant)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_set_variant")
 
     def set_precision(self, mode: int):
         rc = sqh_set_precision(self.ctx, mode)

@@ -67,6 +67,54 @@ def load_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def _counter_per_dispatch(run_dir: str, counter: str, name_part: str) -> tuple:
+    """Average over dispatches of `counter` (summed over its instances) for
+    the kernels whose name contains name_part, from a rocprofv3 --pmc
+    directory (its *counter_collection.csv)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    per = {}
+    for path in files:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter or name_part not in row.get("Kernel_Name", ""):
+                    continue
+                key = (path, row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r} in {run_dir}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def write_traffic(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+                  copy_bytes: int = 160_000_000) -> dict:
+    """HBM bytes per launch of the hull kernel from two counter runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for a device-to-device copy of copy_bytes in each
+    direction; written to profiles/traffic.json with the build's fingerprint."""
+    kname = "k_hull"
+    f_k, nk = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", kname)
+    w_k, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", kname)
+    f_c, nc = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copy")
+    w_c, _ = _counter_per_dispatch(copy_write_dir, "WRITE_SIZE", "copy")
+    ff = copy_bytes / (f_c * 1024.0)
+    fw = copy_bytes / (w_c * 1024.0)
+    rec = {
+        "build": library_fingerprint(),
+        "bytes_per_launch": int(f_k * 1024.0 * ff + w_k * 1024.0 * fw),
+        "fetch_kib": round(f_k, 1), "write_kib": round(w_k, 1), "dispatches": nk,
+        "copy_fetch_kib": round(f_c, 1), "copy_write_kib": round(w_c, 1), "copy_dispatches": nc,
+        "fetch_scale": round(ff, 4), "write_scale": round(fw, 4),
+    }
+    with open(PROFILE_TRAFFIC, "w") as f:
+        json.dump({KERNEL: rec}, f, indent=1)
+        f.write("\n")
+    return rec
+
+
 def library_fingerprint() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -158,10 +206,14 @@ def bench_batched(H, sqh, torch, workloads, total, steps: int, warmup: int, seed
 
 def bench_breakdown(H, sqh, torch, workloads, steps: int = 5, warmup: int = 2) -> list:
     """Per-phase device time of single hulls at the paper's sizes (1M .. 20M
-    points, square and disk), plain and with each pre-filter: the phase
-    times come from the kernel's own clock stamps, the total from HIP events."""
-    modes = (("plain", sqh.SQH_PREFILTER_NONE), ("quad", sqh.SQH_PREFILTER_QUAD),
-             ("octagon", sqh.SQH_PREFILTER_OCTAGON))
+    points, square and disk), plain, with each pre-filter and in the sorted-
+    chain layout: the phase times come from the kernels' own clock stamps,
+    the total from HIP events. sort_bytes: the radix sort's algorithmic
+    traffic (4 passes x (4 B key read + 12 B read + 12 B write) per point)."""
+    modes = (("plain", sqh.SQH_PREFILTER_NONE, sqh.SQH_VARIANT_PARTITION),
+             ("quad", sqh.SQH_PREFILTER_QUAD, sqh.SQH_VARIANT_PARTITION),
+             ("octagon", sqh.SQH_PREFILTER_OCTAGON, sqh.SQH_VARIANT_PARTITION),
+             ("sorted", sqh.SQH_PREFILTER_NONE, sqh.SQH_VARIANT_SORTED))
     dev = torch.device("cuda", 0)
     rows = []
     for kind in ("square", "disk"):
@@ -169,21 +221,30 @@ def bench_breakdown(H, sqh, torch, workloads, steps: int = 5, warmup: int = 2) -
             xy_d = torch.from_numpy(workloads.make(kind, n, 0)).to(dev)
             out = torch.empty(n, dtype=torch.int32, device=dev)
             H.workspace(n, 1)
-            for name, mode in modes:
+            for name, mode, variant in modes:
                 H.set_prefilter(mode)
+                H.set_variant(variant)
                 for _ in range(warmup):
                     H.hull(xy_d, out=out)
                 acc = {}
                 for _ in range(steps):
                     H.hull(xy_d, out=out)
                     st = H.stats()
-                    for k in ("ms_kernel", "ms_prefilter", "ms_seed", "ms_split", "ms_first", "ms_pass", "ms_emit"):
+                    for k in ("ms_kernel", "ms_prefilter", "ms_seed", "ms_split", "ms_first", "ms_sort", "ms_pass",
+                              "ms_emit"):
                         acc[k] = acc.get(k, 0.0) + st[k] / steps
-                rows.append({"kind": kind, "n": n, "mode": name,
-                             "Mpoints_per_s": round(n / (acc["ms_kernel"] / 1000.0) / 1e6, 1),
-                             "subset": int(st["prefilter_points"]),
-                             **{k[3:]: round(v, 4) for k, v in acc.items()}})
+                row = {"kind": kind, "n": n, "mode": name,
+                       "Mpoints_per_s": round(n / (acc["ms_kernel"] / 1000.0) / 1e6, 1),
+                       "subset": int(st["prefilter_points"]), "passes": int(st["passes"]),
+                       "survivors_total": int(st["survivors_total"]),
+                       **{k[3:]: round(v, 4) for k, v in acc.items()}}
+                if variant == sqh.SQH_VARIANT_SORTED:
+                    row["sorted_points"] = int(st["sorted_points"])
+                    row["sort_violations"] = int(st["sort_violations"])
+                    row["sort_bytes"] = 112 * max(int(st["sorted_points"]), 0)
+                rows.append(row)
             H.set_prefilter(sqh.SQH_PREFILTER_NONE)
+            H.set_variant(sqh.SQH_VARIANT_PARTITION)
             del xy_d, out
     return rows
 
@@ -345,7 +406,16 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of the 20M-point input "
                          "(160 MB read + 160 MB written per launch), to scale HBM counters")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                          "COPY_WRITE_DIR"),
+                    help="no GPU work: turn four rocprofv3 --pmc result directories (FETCH_SIZE and "
+                         "WRITE_SIZE of this bench, then of --copy-calibration) into "
+                         "profiles/traffic.json")
     args = ap.parse_args()
+
+    if args.write_traffic:
+        print(json.dumps(write_traffic(*args.write_traffic)), flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -1865,6 +1865,7 @@ done:
 // counts pairs out of order; 0 expected).
 constexpr int kSortSegs = 4;        // segments after the first compaction of one set
 constexpr int kSortBuckets = 1024;  // 2 segment bits + 8 digit bits
+constexpr int kSortRows = 4;        // rows of loads in flight per wave
 
 // the segment of position q: vs[k] is segment k's first position (vs[S..4] = V)
 __device__ __forceinline__ int sort_seg(int q, const int (&vs)[kSortSegs + 1])
@@ -1937,17 +1938,25 @@ __global__ __launch_bounds__(kBlock) void k_sort(HullArgs a)
             // 1. per-wave counts of this wave's part
             for (int i = t; i < kWaves * nbk; i += kBlock) wtab[i / nbk][i % nbk] = 0;
             __syncthreads();
-            for (int q0 = wb; q0 < we; q0 += 64) {
-                const int q = q0 + lane;
-                const bool valid = q < we;
-                int bucket = 0;
-                if (valid) {
-                    const int sg = sort_seg(q, vs);
-                    bucket = (int)((sort_key(gld(a.X[src] + sort_slot(q, sg, vs, off)), sg, desc) >> shift) & 255u);
-                    bucket |= sg << 8;
+            for (int q0 = wb; q0 < we; q0 += 64 * kSortRows) {
+                float xr[kSortRows];
+#pragma unroll
+                for (int r = 0; r < kSortRows; ++r) {  // loads first
+                    const int q = q0 + 64 * r + lane;
+                    xr[r] = q < we ? gld(a.X[src] + sort_slot(q, sort_seg(q, vs), vs, off)) : 0.0f;
                 }
-                const uint64_t m = sort_match(bucket, valid, nbits);
-                if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);  // the group's last lane
+#pragma unroll
+                for (int r = 0; r < kSortRows; ++r) {
+                    const int q = q0 + 64 * r + lane;
+                    const bool valid = q < we;
+                    int bucket = 0;
+                    if (valid) {
+                        const int sg = sort_seg(q, vs);
+                        bucket = (int)((sort_key(xr[r], sg, desc) >> shift) & 255u) | (sg << 8);
+                    }
+                    const uint64_t m = sort_match(bucket, valid, nbits);
+                    if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);  // the group's last lane
+                }
             }
             __syncthreads();
             // 2. per bucket: prefixes over the waves (kept), the workgroup's count
@@ -1986,29 +1995,40 @@ __global__ __launch_bounds__(kBlock) void k_sort(HullArgs a)
                 __syncthreads();
             }
             // 5. stable scatter, row by row
-            for (int q0 = wb; q0 < we; q0 += 64) {
-                const int q = q0 + lane;
-                const bool valid = q < we;
-                float x = 0.0f, y = 0.0f;
-                int id = 0, bucket = 0;
-                if (valid) {
-                    const int sg = sort_seg(q, vs);
-                    const int sl = sort_slot(q, sg, vs, off);
-                    x = gld(a.X[src] + sl);
-                    y = gld(a.Y[src] + sl);
-                    id = gld(a.I[src] + sl);
-                    bucket = (int)((sort_key(x, sg, desc) >> shift) & 255u);
-                    bucket |= sg << 8;
+            for (int q0 = wb; q0 < we; q0 += 64 * kSortRows) {
+                float xr[kSortRows], yr[kSortRows];
+                int ir[kSortRows];
+#pragma unroll
+                for (int r = 0; r < kSortRows; ++r) {  // loads first
+                    const int q = q0 + 64 * r + lane;
+                    xr[r] = yr[r] = 0.0f;
+                    ir[r] = 0;
+                    if (q < we) {
+                        const int sl = sort_slot(q, sort_seg(q, vs), vs, off);
+                        xr[r] = gld(a.X[src] + sl);
+                        yr[r] = gld(a.Y[src] + sl);
+                        ir[r] = gld(a.I[src] + sl);
+                    }
                 }
-                const uint64_t m = sort_match(bucket, valid, nbits);
-                int pos = 0;
-                if (valid) pos = wtab[w][bucket] + __popcll(m & mask_lt(lane));
-                if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);
-                if (valid) {
-                    const int dl = sort_slot(pos, sort_seg(pos, vs), vs, off);
-                    gst(a.X[dst] + dl, x);
-                    gst(a.Y[dst] + dl, y);
-                    gst(a.I[dst] + dl, id);
+#pragma unroll
+                for (int r = 0; r < kSortRows; ++r) {
+                    const int q = q0 + 64 * r + lane;
+                    const bool valid = q < we;
+                    int bucket = 0;
+                    if (valid) {
+                        const int sg = sort_seg(q, vs);
+                        bucket = (int)((sort_key(xr[r], sg, desc) >> shift) & 255u) | (sg << 8);
+                    }
+                    const uint64_t m = sort_match(bucket, valid, nbits);
+                    int pos = 0;
+                    if (valid) pos = wtab[w][bucket] + __popcll(m & mask_lt(lane));
+                    if (valid && (m >> lane) == 1ull) wtab[w][bucket] += __popcll(m);
+                    if (valid) {
+                        const int dl = sort_slot(pos, sort_seg(pos, vs), vs, off);
+                        gst(a.X[dst] + dl, xr[r]);
+                        gst(a.Y[dst] + dl, yr[r]);
+                        gst(a.I[dst] + dl, ir[r]);
+                    }
                 }
             }
             grid_sync(a.bar, a.err);

@@ -86,9 +86,10 @@ typedef struct sqh_stats {
     int64_t cmp_exact;        /* farthest-point comparisons decided exactly */
     int64_t hull_size;        /* total hull vertices (all sets) */
     int64_t max_segments;     /* largest number of active segments in a pass */
-    double  ms_total;         /* device time of the whole call: workspace reset + hull kernel */
-    double  ms_kernel;        /* the persistent hull kernel alone */
-    double  ms_seed, ms_split, ms_first, ms_pass, ms_emit;  /* phases of the hull kernel */
+    double  ms_total;         /* device time of the whole call: workspace reset + the cooperative launches */
+    double  ms_kernel;        /* the cooperative launches alone (pre-filter, hull kernel; sorted variant:
+                                 first phases, sort, passes) */
+    double  ms_seed, ms_split, ms_first, ms_pass, ms_emit;  /* phases of the hull kernel (its own clock) */
     double  ms_prefilter;     /* the pre-filter's two phases (extremes, compaction) */
     int64_t prefilter_points; /* points kept by the pre-filter plus its corners; -1: not run */
     int64_t pass_points[SQH_MAX_TIMED_PASSES];    /* points entering pass k */

@@ -1405,7 +1405,13 @@ __device__ __forceinline__ void emit_small(const HullArgs& a, int h, int2* lds)
         for (int j = 0; j < h; ++j) rank += lds[j].x < key;
         if (rank < a.cap) gst(a.out + rank, lds[i].y);
     }
-    if (threadIdx.x == 0) a.info->h_total = h;
+    if (threadIdx.x == 0) {
+        a.info->h_total = h;
+        if (a.out_off) {  // a batched call on one set
+            a.out_off[0] = 0;
+            a.out_off[1] = h;
+        }
+    }
     __syncthreads();
 }
 

@@ -200,3 +200,17 @@ def test_full_batch_4096_sets(H):
     for s in range(b.nsets):
         got = out[out_off[s]:out_off[s + 1]]
         assert [int(v) for v in got] == [int(v) for v in oracle.c_hull(b.set(s))], s
+
+
+def test_batch_of_one_set(H):
+    # one set through the batched entry point: few vertices (one-workgroup
+    # emission) and many (grid emission) both fill the caller's offsets
+    import torch
+    for kind, n, seed in (("disk", 250_000, 51), ("circle", 200_000, 53)):
+        say(f"batch of one set: {kind} n={n}")
+        xy = workloads.make(kind, n, seed)
+        want = [int(v) for v in oracle.c_hull(xy)]
+        off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
+        out, out_off = H.hull_batched(torch.from_numpy(xy).cuda(), off)
+        assert [int(v) for v in out_off.cpu().numpy()] == [0, len(want)], kind
+        assert [int(v) for v in out[: len(want)].cpu().numpy()] == want, kind

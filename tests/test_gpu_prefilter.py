@@ -128,3 +128,38 @@ def test_non_finite_rejected(H, n):
     # the next call on the same workspace is clean
     xy = workloads.disk(n, 5)
     assert gpu_hull(H, xy) == expect(xy)
+
+
+def test_graph_replays(H):
+    import torch
+    say(f"{H.mode_name}: graph replays")
+    xy = workloads.square(400_000, 41)
+    t = torch.from_numpy(xy).cuda()
+    want = expect(xy)
+    g = H.graph(t)
+    try:
+        for rep in range(3):
+            g.launch()
+            out, _ = g.result()
+            assert [int(v) for v in out.cpu().numpy()] == want, rep
+            assert gpu_hull(H, xy) == want  # eager work between the replays
+            torch.cuda.synchronize()
+        # other points in the same buffer
+        xy2 = workloads.disk(400_000, 43)
+        t.copy_(torch.from_numpy(xy2))
+        g.launch()
+        out, _ = g.result()
+        assert [int(v) for v in out.cpu().numpy()] == expect(xy2)
+    finally:
+        g.close()
+
+
+def test_batch_of_one_set(H):
+    import torch
+    say(f"{H.mode_name}: batch of one set")
+    xy = workloads.square(300_000, 47)
+    off = torch.tensor([0, len(xy)], dtype=torch.int64, device="cuda")
+    out, out_off = H.hull_batched(torch.from_numpy(xy).cuda(), off)
+    got = [int(v) for v in out[: int(out_off[1])].cpu().numpy()]
+    assert got == expect(xy)
+    assert 0 <= H.stats()["prefilter_points"] < len(xy)

@@ -164,3 +164,29 @@ def test_non_finite_rejected(H):
     xy = workloads.disk(100_000, 5)
     assert gpu_hull(H, xy) == expect(xy)
     check_sort(H)
+
+
+def test_batch_of_one_set(H):
+    # a batched call on one set takes the same launch chain as sqh_hull
+    import torch
+    say(f"{H.cfg_name}: batch of one set")
+    xy = workloads.disk(250_000, 31)
+    off = torch.tensor([0, len(xy)], dtype=torch.int64, device="cuda")
+    out, out_off = H.hull_batched(torch.from_numpy(xy).cuda(), off)
+    got = [int(v) for v in out[: int(out_off[1])].cpu().numpy()]
+    assert got == expect(xy)
+    check_sort(H)
+
+
+def test_autotune_keeps_the_hull(H):
+    import torch
+    say(f"{H.cfg_name}: autotune")
+    xy = workloads.square(500_000, 37)
+    t = torch.from_numpy(xy).cuda()
+    try:
+        text = H.autotune(t, reps=1)
+        assert '"log2n": 18' in text, text
+        assert gpu_hull(H, xy) == expect(xy)
+        check_sort(H)
+    finally:
+        H.set_tuning('{"entries": []}')

@@ -249,6 +249,13 @@ def bench_breakdown(H, sqh, torch, workloads, steps: int = 5, warmup: int = 2) -
     return rows
 
 
+def modes_at(rows: list, kind: str, n: int) -> dict:
+    """Kernel throughput of each method variant (plain, pre-filters, sorted
+    layout) on the benchmarked workload, taken from the breakdown rows."""
+    return {r["mode"]: {"Mpoints_per_s": r["Mpoints_per_s"], "ms_kernel": r["kernel"]}
+            for r in rows if r["kind"] == kind and r["n"] == n}
+
+
 def _percentiles(lat_ms):
     import numpy as np
     v = np.asarray(lat_ms, dtype=np.float64)
@@ -521,6 +528,7 @@ def main() -> int:
         line["serving"] = bench_serving(H, sqh, torch, workloads, count=args.serve)
     if not args.no_breakdown:
         line["breakdown"] = bench_breakdown(H, sqh, torch, workloads)
+        line["modes"] = modes_at(line["breakdown"], args.kind, args.n)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(xy)
     else:

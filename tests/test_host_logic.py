@@ -105,3 +105,13 @@ def test_prefilter_line_test_bound():
                 certified += 1
                 assert exact > 0, (trial, k)
     assert certified > 100
+
+
+def test_modes_at_picks_the_workload_rows():
+    rows = [{"kind": "square", "n": 20, "mode": "plain", "Mpoints_per_s": 3.0, "kernel": 0.5},
+            {"kind": "square", "n": 20, "mode": "sorted", "Mpoints_per_s": 1.0, "kernel": 1.5},
+            {"kind": "square", "n": 10, "mode": "plain", "Mpoints_per_s": 9.0, "kernel": 0.1},
+            {"kind": "disk", "n": 20, "mode": "plain", "Mpoints_per_s": 2.0, "kernel": 0.7}]
+    assert bench.modes_at(rows, "square", 20) == {"plain": {"Mpoints_per_s": 3.0, "ms_kernel": 0.5},
+                                                   "sorted": {"Mpoints_per_s": 1.0, "ms_kernel": 1.5}}
+    assert bench.modes_at(rows, "circle", 20) == {}

@@ -126,25 +126,62 @@ def library_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
+def host_threads() -> int:
+    """Threads the CPU baseline may use: every core the process may run on,
+    at most the job's thread allowance (OMP_NUM_THREADS where it is set)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
 def cpu_baseline(xy, budget_s: float = 25.0) -> dict:
+    """The C oracle on this host: built for this machine (-march=native, else
+    the portable in-tree build), timed on one core and on all the cores the
+    job may use (contiguous index ranges at once, then the hull of their
+    hulls; the result is checked against the one-core result)."""
+    import tempfile
+    import numpy as np
     import oracle
     n = len(xy)
-    times = []
-    t_start = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        oracle.c_hull(xy)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 3:
-            break
-    med = statistics.median(times)
+    lib, build = None, "portable in-tree build (-march=x86-64-v2)"
+    try:
+        d = tempfile.mkdtemp(prefix="sqh_oracle_")
+        lib = oracle.load_lib(oracle.build(force=True, path=os.path.join(d, "liboracle_native.so"), native=True))
+        build = "gcc -O3 -march=native"
+    except Exception as e:  # compiler missing or the flag refused: time the portable build
+        build += f" (native build failed: {type(e).__name__})"
+    threads = host_threads()
+
+    def timed(fn, cap):
+        times, res = [], None
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            res = fn()
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start + times[-1] > budget_s / 2 or len(times) >= cap:
+                break
+        return statistics.median(times), len(times), res
+
+    t1, r1, h1 = timed(lambda: oracle.c_hull(xy, lib), 3)
+    tN, rN, hN = timed(lambda: oracle.c_hull_sharded(xy, threads, lib), 5)
+    same = bool(np.array_equal(h1, hN))
     return {
-        "value": round(n / med / 1e6, 3),
+        "value": round(n / tN / 1e6, 3),
         "unit": "Mpoints/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"C monotone chain (exact predicates) on the same {n}-point input, "
-                  f"{len(times)} run(s), median {med:.2f} s",
+        "sample": f"C monotone chain (exact predicates), {build}, on the same {n}-point input: "
+                  f"{threads} threads on contiguous index ranges plus the hull of their hulls, "
+                  f"median of {rN} run(s) {tN:.2f} s; one core: median of {r1} run(s) {t1:.2f} s",
+        "single_core_value": round(n / t1 / 1e6, 3),
+        "nproc": os.cpu_count(),
+        "threads_identical_to_one_core": same,
     }
 
 

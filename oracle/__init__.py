@@ -24,16 +24,31 @@ SRC_PATH = os.path.join(HERE, "monotone_chain.c")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
+def build(force: bool = True, path: str | None = None, native: bool = False) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FMA contraction).
+
+    The in-tree copy is built for a portable x86-64 level (it is built on one
+    machine and may run on another); ``native=True`` builds a copy for the
+    machine it runs on (the timed CPU baseline)."""
+    path = path or LIB_PATH
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
         subprocess.check_call([
-            "gcc", "-O3", "-march=x86-64-v2", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-std=c11", "-o", tmp, SRC_PATH, "-lm",
+            "gcc", "-O3", "-march=native" if native else "-march=x86-64-v2", "-ffp-contract=off",
+            "-fno-fast-math", "-fPIC", "-shared", "-std=c11", "-o", tmp, SRC_PATH, "-lm",
         ])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, path)
+    return path
+
+
+def load_lib(path: str) -> ctypes.CDLL:
+    lib = ctypes.CDLL(path)
+    lib.oracle_hull.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_hull.restype = ctypes.c_int
+    lib.oracle_orient_sign.argtypes = [ctypes.c_float] * 6
+    lib.oracle_orient_sign.restype = ctypes.c_int
+    return lib
 
 
 def _load():
@@ -41,13 +56,7 @@ def _load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        lib = ctypes.CDLL(LIB_PATH)
-        lib.oracle_hull.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
-        lib.oracle_hull.restype = ctypes.c_int
-        lib.oracle_orient_sign.argtypes = [ctypes.c_float] * 6
-        lib.oracle_orient_sign.restype = ctypes.c_int
-        _lib = lib
+        _lib = load_lib(LIB_PATH)
     return _lib
 
 
@@ -55,16 +64,35 @@ class OracleError(RuntimeError):
     pass
 
 
-def c_hull(xy: np.ndarray) -> np.ndarray:
-    """Hull indices (int32) from the C oracle."""
+def c_hull(xy: np.ndarray, lib: ctypes.CDLL | None = None) -> np.ndarray:
+    """Hull indices (int32) from the C oracle (``lib``: another build of it)."""
     a = np.ascontiguousarray(np.asarray(xy, dtype=np.float32).reshape(-1, 2))
     n = a.shape[0]
     out = np.empty(max(n, 1), dtype=np.int32)
     h = ctypes.c_int64(0)
-    rc = _load().oracle_hull(a.ctypes.data, n, out.ctypes.data, out.shape[0], ctypes.byref(h))
+    rc = (lib or _load()).oracle_hull(a.ctypes.data, n, out.ctypes.data, out.shape[0], ctypes.byref(h))
     if rc != 0:
         raise OracleError(f"oracle_hull returned {rc}")
     return out[:h.value].copy()
+
+
+def c_hull_sharded(xy: np.ndarray, threads: int, lib: ctypes.CDLL | None = None) -> np.ndarray:
+    """The same hull on ``threads`` host threads: the C oracle on contiguous
+    index ranges at once (ctypes releases the GIL during the call), then once
+    more on the union of the range hulls, whose hull is the hull of all
+    points. Ranges are in index order and each range hull names the lowest
+    index at its positions, so the first copy of a position in the union is
+    its lowest input index, as the oracle's tie rule requires."""
+    from concurrent.futures import ThreadPoolExecutor
+    a = np.ascontiguousarray(np.asarray(xy, dtype=np.float32).reshape(-1, 2))
+    n = a.shape[0]
+    threads = max(1, min(int(threads), max(n, 1)))
+    cuts = [n * k // threads for k in range(threads + 1)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda k: c_hull(a[cuts[k]:cuts[k + 1]], lib) + cuts[k], range(threads)))
+    ids = np.concatenate(parts).astype(np.int64) if parts else np.zeros(0, np.int64)
+    local = c_hull(a[ids], lib)
+    return ids[local].astype(np.int32)
 
 
 def c_orient_sign(a, b, c) -> int:

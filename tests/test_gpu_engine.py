@@ -213,3 +213,47 @@ def test_engine_admit_while_step_in_flight(H):
             assert [int(v) for v in results[i]] == expect_hull(xy), i
     finally:
         E.close()
+
+
+def serving_requests(seed, count, lo=1_000_000, hi=4_000_000):
+    """Requests from the upper part of the serving size range (log-uniform),
+    kinds square/disk/circle as the serving workload draws them."""
+    rng = np.random.default_rng(seed)
+    kinds = ["square", "disk", "circle"]
+    out = []
+    for i in range(count):
+        n = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        out.append(workloads.make(kinds[int(rng.integers(0, 3))], n, seed * 1000 + i))
+    return out
+
+
+def test_engine_large_requests_alone_and_mixed(H):
+    # 1M .. 4M-point requests: each alone, then all of them in flight at once
+    # with admissions staggered over the steps; every result is the oracle's
+    reqs = serving_requests(21, 5)
+    say("engine: large requests " + ", ".join(str(len(r)) for r in reqs))
+    want = [[int(v) for v in oracle.c_hull(xy)] for xy in reqs]
+    E = H.engine(1 << 24, 64, 1 << 23)
+    try:
+        for i, xy in enumerate(reqs):
+            results = {}
+            assert E.admit(xy, i)
+            for _ in range(400):
+                drain(E, results, 4)
+                if i in results:
+                    break
+            assert [int(v) for v in results[i]] == want[i], ("alone", i, len(xy))
+        results = {}
+        pending = list(range(len(reqs)))
+        steps = 0
+        while len(results) < len(reqs):
+            if pending and E.admit(reqs[pending[0]], 100 + pending[0]):
+                pending.pop(0)
+            drain(E, results, 2)
+            steps += 1
+            assert steps < 4000
+        for i in range(len(reqs)):
+            assert [int(v) for v in results[100 + i]] == want[i], ("mixed", i, len(reqs[i]))
+        assert E.status()["free_slots"] == E.slots
+    finally:
+        E.close()

@@ -118,6 +118,15 @@ def test_workloads_1m(H, kind, n):
     assert gpu_hull(H, xy) == [int(v) for v in oracle.c_hull(xy)]
 
 
+@pytest.mark.parametrize("kind", ["square", "disk"])
+@pytest.mark.parametrize("n", [5_000_000, 10_000_000])
+def test_workloads_5m_10m(H, kind, n):
+    # the remaining sizes of the single-hull workload (plain path)
+    say(f"{kind} n={n} seed 0")
+    xy = workloads.make(kind, n, 0)
+    assert gpu_hull(H, xy) == [int(v) for v in oracle.c_hull(xy)]
+
+
 def test_fp64_only_identical(H):
     say("fp64-only mode")
     xy = workloads.circle(300_000, 3)
@@ -200,6 +209,29 @@ def test_full_batch_4096_sets(H):
     for s in range(b.nsets):
         got = out[out_off[s]:out_off[s + 1]]
         assert [int(v) for v in got] == [int(v) for v in oracle.c_hull(b.set(s))], s
+
+
+def test_batch_with_large_sets(H):
+    # sets of 150K .. 1M points (the upper part of the batch's log-uniform
+    # size range) mixed with small ones in one batched call
+    import torch
+    rng = np.random.default_rng(44)
+    big = [int(v) for v in np.floor(np.exp(rng.uniform(np.log(150_000), np.log(1_000_000), size=10)))]
+    small = [int(v) for v in np.floor(np.exp(rng.uniform(np.log(64), np.log(150_000), size=22)))]
+    sizes = big + small
+    rng.shuffle(sizes)
+    kinds = ["square", "disk", "circle"]
+    parts = [workloads.make(kinds[int(rng.integers(0, 3))], s, 500 + i) for i, s in enumerate(sizes)]
+    say(f"batch with large sets: {len(sizes)} sets, {sum(sizes)} points, largest {max(sizes)}")
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    xy = np.concatenate(parts, 0).astype(np.float32)
+    out, out_off = H.hull_batched(torch.from_numpy(xy).cuda(), torch.from_numpy(off).cuda())
+    out = out.cpu().numpy()
+    out_off = out_off.cpu().numpy()
+    for s, p in enumerate(parts):
+        got = [int(v) for v in out[out_off[s]:out_off[s + 1]]]
+        assert got == [int(v) for v in oracle.c_hull(p)], (s, len(p))
 
 
 def test_batch_of_one_set(H):

@@ -232,15 +232,96 @@ MUTANTS = {
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistakes_are_caught(name):
+    # each mutant must be caught by the brute-force pin and, on its own, by
+    # the invariant checker (which is the only pin at large n)
     mutant = MUTANTS[name]
-    caught = False
+    by_brute = by_check = False
     for path in sorted(glob.glob(os.path.join(GOLDEN, "*.txt"))):
         xy, expect = load_golden(path)
         got = mutant(xy)
-        bad = got != he.brute_force_hull(xy)
+        by_brute |= got != he.brute_force_hull(xy)
         try:
             he.check_hull(xy, got)
         except AssertionError:
-            bad = True
-        caught |= bad
-    assert caught, f"mutant '{name}' passed every pin"
+            by_check = True
+    assert by_brute, f"mutant '{name}' passed the brute-force pin"
+    assert by_check, f"mutant '{name}' passed check_hull"
+
+
+# ---- check_hull's own pins: wrong answers that break exactly one of the
+# properties defining the hull, each of which check_hull must reject ----
+
+def _square_interior():
+    return load_golden(os.path.join(GOLDEN, "square_interior.txt"))
+
+
+def _rejects(xy, h, what):
+    with pytest.raises(AssertionError, match=what):
+        he.check_hull(xy, h)
+
+
+def test_check_hull_accepts_the_answer():
+    xy, expect = _square_interior()
+    he.check_hull(xy, expect)
+
+
+def test_check_hull_rejects_a_point_outside():
+    # a strictly convex counter-clockwise triangle of input points from the
+    # lexicographic minimum, one corner left out: only containment fails
+    xy, expect = _square_interior()
+    _rejects(xy, [6, 7, 8], "outside edge")
+    _rejects(xy, [6, 8, 9], "outside edge")
+
+
+def test_check_hull_rejects_a_collinear_vertex():
+    # the edge midpoint (0.5, 0) (index 2) between (0,0) and (1,0): inside
+    # or on every edge, distinct positions, but not strictly convex
+    xy, expect = _square_interior()
+    _rejects(xy, [6, 2, 7, 8, 9], "strictly convex")
+
+
+def test_check_hull_rejects_clockwise_order():
+    xy, expect = _square_interior()
+    _rejects(xy, [6, 9, 8, 7], "strictly convex|outside edge")
+
+
+def test_check_hull_rejects_a_wrong_start():
+    xy, expect = _square_interior()
+    _rejects(xy, expect[1:] + expect[:1], "lexicographically smallest")
+
+
+def test_check_hull_rejects_a_higher_duplicate_index():
+    # duplicates.txt: (4,0) at indices 0 and 4; index 4 is not the lowest
+    xy, expect = load_golden(os.path.join(GOLDEN, "duplicates.txt"))
+    assert expect == [3, 0, 1]
+    _rejects(xy, [3, 4, 1], "lowest index")
+
+
+def test_check_hull_rejects_a_repeated_vertex():
+    xy, expect = _square_interior()
+    _rejects(xy, expect + [expect[1]], "repeated position")
+
+
+def test_check_hull_rejects_index_out_of_range():
+    xy, expect = _square_interior()
+    _rejects(xy, [6, 7, 8, 10], "out of range")
+
+
+def test_check_hull_rejects_wrong_degenerate_answers():
+    xy, expect = load_golden(os.path.join(GOLDEN, "collinear.txt"))
+    assert expect == [1, 2]
+    _rejects(xy, [1, 0], "lexmax")           # an interior point as the far end
+    _rejects(xy, [1], "several distinct positions")
+    tri = np.array([[0, 0], [1, 0], [0, 1]], np.float32)
+    _rejects(tri, [0, 1], "lexmax|off the line")
+
+
+@pytest.mark.parametrize("kind", ["square", "disk", "circle", "grid"])
+def test_sharded_oracle_equals_one_call(kind):
+    # the all-core timing leg: range hulls, then the hull of their union,
+    # must give the one-call result exactly (duplicates across ranges too)
+    xy = workloads.make(kind, 50_000, 17)
+    for threads in (1, 3, 8):
+        assert np.array_equal(oracle.c_hull_sharded(xy, threads), oracle.c_hull(xy))
+    dup = np.concatenate([xy[:100], xy[:100], xy[:100]])
+    assert np.array_equal(oracle.c_hull_sharded(dup, 3), oracle.c_hull(dup))

@@ -15,6 +15,7 @@
 
 #include "../../include/sqh.h"
 #include "sqh_kernels.hip"
+#include "sqh_stream.hip"
 #include "sqh_engine.hip"
 
 using namespace sqh;
@@ -31,7 +32,7 @@ struct Layout {
     size_t x[2], y[2], id[2];
     size_t gstart, sets, recs, rec_cid, segs[2], seg_cid[2], vstart[2];
     size_t bitmap, vidx, vlist, wprefix, slots, ctab, bar, err, stats, sv, info;
-    size_t ext, xy2, ids2, gs2, shist, stot;
+    size_t ext, xy2, ids2, gs2, shist, stot, sws;
     int64_t vcap;
     size_t bytes;
 };
@@ -84,6 +85,8 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     // sorted-chain variant: bucket counts per workgroup and totals
     L.shist = take(sizeof(int) * (size_t)kSortBuckets * (size_t)kMaxGrid);
     L.stot = take(sizeof(int) * (size_t)kSortBuckets);
+    // streaming path of one large set: partial results and one count word per tile
+    L.sws = take(sizeof(StreamWs) + sizeof(uint64_t) * (size_t)((N + kSTile - 1) / kSTile + 64));
     L.bytes = o;
     return true;
 }
@@ -113,6 +116,7 @@ struct sqh_ctx {
     int engine_grid = 0;  // workgroups of an engine step (0: all but 1/8 of the co-resident ones)
     int prefilter = 0;    // SQH_PREFILTER_*
     int variant = 0;      // SQH_VARIANT_*
+    int stream = 1;       // large single hulls take the streaming path (SQH_STREAM=0 turns it off)
 };
 
 struct sqh_graph {
@@ -216,6 +220,13 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.xy2 = static_cast<float2*>(at(L.xy2));
     a.ids2 = static_cast<int*>(at(L.ids2));
     a.gs2 = static_cast<int*>(at(L.gs2));
+    a.sws = at(L.sws);
+    a.sdone = static_cast<StreamWs*>(a.sws)->done;
+    // one large set in plain mode, 16-byte aligned input: the streaming path
+    a.stream = (ctx->stream && nsets == 1 && N >= kStreamMin && !a.prefilter && !a.sorted &&
+                (reinterpret_cast<uintptr_t>(d_xy) & 15u) == 0)
+                   ? 1
+                   : 0;
     const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
     reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
     return SQH_OK;
@@ -226,9 +237,22 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
 // reads the pre-filter's subset only where the pre-filter runs), or for the
 // sorted-chain variant its first phases, k_sort and its passes.
 inline bool pre_runs(const HullArgs& a) { return a.prefilter && a.G == 1 && a.N > 0; }
-inline int coop_launches(const HullArgs& a, const void* (&f)[4])
+// coop[i] = 0: kernel i never waits for other workgroups (an ordinary
+// launch, which starts without the cooperative launch's queue round trip).
+inline int coop_launches(const HullArgs& a, const void* (&f)[4], int (&coop)[4])
 {
     int n = 0;
+    for (int i = 0; i < 4; ++i) coop[i] = 1;
+    if (a.stream) {
+        coop[n] = 0;
+        f[n++] = reinterpret_cast<const void*>(k_sseed);
+        coop[n] = 0;
+        f[n++] = reinterpret_cast<const void*>(k_ssplit);
+        coop[n] = 0;
+        f[n++] = reinterpret_cast<const void*>(k_sfirst);
+        f[n++] = reinterpret_cast<const void*>(k_hull<kHullPasses>);
+        return n;
+    }
     if (pre_runs(a)) f[n++] = reinterpret_cast<const void*>(k_prefilter);
     if (a.sorted && a.G == 1) {
         f[n++] = reinterpret_cast<const void*>(k_hull<kHullFirst>);
@@ -250,8 +274,12 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
     const void* f[4];
-    const int nf = coop_launches(a, f);
-    for (int i = 0; i < nf; ++i) HIP_OK(hipLaunchCooperativeKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
+    int coop[4];
+    const int nf = coop_launches(a, f, coop);
+    for (int i = 0; i < nf; ++i) {
+        if (coop[i]) HIP_OK(hipLaunchCooperativeKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
+        else HIP_OK(hipLaunchKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
+    }
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
 }
@@ -537,7 +565,9 @@ int sqh_create(sqh_ctx** out, int device)
                               reinterpret_cast<const void*>(k_hull<kHullPre>),
                               reinterpret_cast<const void*>(k_hull<kHullFirst>),
                               reinterpret_cast<const void*>(k_hull<kHullPasses>),
-                              reinterpret_cast<const void*>(k_prefilter), reinterpret_cast<const void*>(k_sort)};
+                              reinterpret_cast<const void*>(k_prefilter), reinterpret_cast<const void*>(k_sort),
+                              reinterpret_cast<const void*>(k_sseed), reinterpret_cast<const void*>(k_ssplit),
+                              reinterpret_cast<const void*>(k_sfirst)};
         for (const void* f : coop) {
             int k = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, kBlock, 0) != hipSuccess) k = 0;
@@ -552,6 +582,8 @@ int sqh_create(sqh_ctx** out, int device)
     {
         const char* t = getenv("SQH_TRACE");
         c->trace = t ? atoi(t) : 0;  // 1: seed and split, 2: first compaction and first pass
+        const char* st = getenv("SQH_STREAM");
+        c->stream = st ? (atoi(st) != 0) : 1;
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->evk) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess ||
@@ -760,7 +792,8 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     bool ok = hipGraphCreate(&g->graph, 0) == hipSuccess &&
               hipGraphAddKernelNode(&prev, g->graph, nullptr, 0, &kp) == hipSuccess;
     const void* f[4];
-    const int nf = coop_launches(g->args, f);
+    int fcoop[4];
+    const int nf = coop_launches(g->args, f, fcoop);
     for (int i = 0; ok && i < nf; ++i) {
         hipKernelNodeParams hp = kp;
         hp.func = const_cast<void*>(f[i]);
@@ -768,7 +801,8 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
         hp.blockDim = dim3(kBlock);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, g->graph, &prev, 1, &hp) == hipSuccess &&
-             hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &coop) == hipSuccess;
+             (!fcoop[i] ||
+              hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &coop) == hipSuccess);
         prev = node;
     }
     ok = ok && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;

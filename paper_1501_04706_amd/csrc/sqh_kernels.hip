@@ -820,6 +820,11 @@ struct HullArgs {
     int sorted;
     int* shist;              // kSortBuckets x workgroups
     int* stot;               // kSortBuckets
+    // streaming path of one large set (k_sseed, k_ssplit, k_sfirst): partial
+    // results and tile count words
+    void* sws;
+    unsigned int* sdone;     // the streaming kernels' completion counters (cleared by k_reset)
+    int stream;              // 1: the streaming kernels run the first phases, k_hull<kHullPasses> the rest
 };
 
 
@@ -2083,6 +2088,7 @@ __global__ void k_reset(HullArgs a)
         a.info->sort_bad = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
+    if (a.stream && gtid < 4) a.sdone[gtid] = 0u;
     for (int i = gtid; i < 4 * kStatSlots; i += gstride) a.stats[i] = 0;
     for (int i = gtid; i < a.W; i += gstride) a.bitmap[i] = 0ull;
     for (int i = gtid; i < 4 * a.G; i += gstride) {

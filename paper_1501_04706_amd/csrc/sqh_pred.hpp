@@ -197,7 +197,8 @@ __device__ __forceinline__ double orient64(float ox, float oy, float ex, float e
 
 // sign of orient(o, e, p), exactly: float64 stage, then the 6-term expansion
 //   ex*py - ex*oy - ox*py - ey*px + ey*ox + oy*px
-__device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey, float px, float py)
+// (the _inl form is for code that must not contain calls)
+__device__ __forceinline__ int orient_exact_inl(float ox, float oy, float ex, float ey, float px, float py)
 {
     double bound;
     const double d = orient64(ox, oy, ex, ey, px, py, bound);
@@ -212,13 +213,17 @@ __device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey,
     t[5] = (double)oy * (double)px;
     return expansion_sign(t);
 }
+__device__ __noinline__ int orient_exact(float ox, float oy, float ex, float ey, float px, float py)
+{
+    return orient_exact_inl(ox, oy, ex, ey, px, py);
+}
 
 // sign of area(P) - area(Q) for the edge o -> e, where area(X) = -orient(o,e,X):
 // float64 stage (areas with their bounds; fl(x) > fl(y) implies x > y), then
 //   (ex-ox)(qy-py) - (ey-oy)(qx-px)
 //   = ex*qy - ex*py - ox*qy + ox*py - ey*qx + ey*px + oy*qx - oy*px
-__device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float ey,
-                                           float px, float py, float qx, float qy)
+__device__ __forceinline__ int area_cmp_exact_inl(float ox, float oy, float ex, float ey,
+                                                  float px, float py, float qx, float qy)
 {
     double bp, bq;
     const double ap = -orient64(ox, oy, ex, ey, px, py, bp);
@@ -235,6 +240,11 @@ __device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float e
     t[6] = (double)oy * (double)qx;
     t[7] = -((double)oy * (double)px);
     return expansion_sign(t);
+}
+__device__ __noinline__ int area_cmp_exact(float ox, float oy, float ex, float ey,
+                                           float px, float py, float qx, float qy)
+{
+    return area_cmp_exact_inl(ox, oy, ex, ey, px, py, qx, qy);
 }
 
 // Filter-only sign: +-1 when certified, 0 when undecided (the exact sign may

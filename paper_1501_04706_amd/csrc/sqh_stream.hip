@@ -1,0 +1,974 @@
+// Streaming path for one large point set (device code, gfx950).
+//
+// k_stream runs the seed, the first split and the first compaction of a
+// single hull (paper sections 4.3 - 4.4) as three streams over the input,
+// one grid barrier each, then leaves the segment table of the first pass in
+// the workspace for k_hull<kHullPasses>, which runs the passes and the
+// emission. Compared with the general persistent kernel (groups of any size,
+// reduce-then-scan phases with two barriers and two reads each), every
+// workgroup here walks whole tiles of 16384 points:
+//   * the input is read as 16-byte loads (two points per lane), eight rows
+//     of them in flight per wave;
+//   * the seed and the split keep private per-lane results (the lane's
+//     lexicographic extremes; side counts and farthest points) that are
+//     reduced once per workgroup; after the barrier every workgroup reduces
+//     the workgroups' partial results itself, so no second barrier is
+//     needed;
+//   * the first compaction reads the input once: tiles are taken in rounds
+//     (round r gives workgroup b tile r * grid + b), each tile publishes its
+//     four bucket counts as one self-validating 64-bit word, and the tile's
+//     output position is the sum of the counts of all earlier tiles (the
+//     earlier rounds' totals, kept by every workgroup, plus the earlier
+//     tiles of its round). Points then go straight from registers to their
+//     child segment, ranked inside a row by ballots so that each row writes
+//     contiguous runs.
+// Farthest-point candidates are kept per lane as an area interval and an
+// input index; the rare comparisons the interval cannot decide fetch the
+// candidate's coordinates from the input and compare exactly (the order of
+// section 4.4.1 with the tie rules of the general kernel, so the result is
+// the same for every tile shape).
+#pragma once
+
+namespace sqh {
+
+constexpr int kSRows = 8;                     // rows of point pairs per wave and tile
+constexpr int kSTilePairs = kBlock * kSRows;  // pairs per workgroup tile
+constexpr int kSTile = 2 * kSTilePairs;       // points per workgroup tile (16384)
+constexpr int kStreamMin = 1 << 20;           // single hulls of at least this many points take this path
+
+// Farthest-point candidate of one lane: the area interval [lo, hi] =
+// [fl(a - w), fl(a + w)] of the float32 estimate a with error bound w, and
+// the input index (-1: none). Rounding is monotone, so lo(P) > hi(Q) proves
+// area(P) > area(Q).
+struct LCand {
+    float lo, hi;
+    int id;
+};
+__device__ __forceinline__ LCand lc_none()
+{
+    LCand c;
+    c.lo = -INFINITY; c.hi = -INFINITY; c.id = -1;
+    return c;
+}
+
+// A candidate with its coordinates (for reductions and the exact order).
+struct FCand {
+    float lo, hi, x, y;
+    int id;
+    int pad[3];
+};
+__device__ __forceinline__ FCand fc_none()
+{
+    FCand c;
+    c.lo = -INFINITY; c.hi = -INFINITY; c.x = 0.0f; c.y = 0.0f; c.id = -1;
+    c.pad[0] = c.pad[1] = c.pad[2] = 0;
+    return c;
+}
+
+// Exact order of two distinct candidates for edge E (section 4.4.1 asks for
+// the farthest point; ties as in the general kernel): exact area, then among
+// equal areas the point earliest along E, then the lower index.
+__device__ __forceinline__ bool beats_exact_xy(const Edge& E, float px, float py, int pid, float qx, float qy, int qid)
+{
+    const int s = area_cmp_exact(E.ox, E.oy, E.ex, E.ey, px, py, qx, qy);
+    if (s != 0) return s > 0;
+    if (px == qx && py == qy) return pid < qid;
+    const bool p_first = (px < qx) || (px == qx && py < qy);
+    return E.fwd ? p_first : !p_first;
+}
+
+__device__ __forceinline__ bool beats_exact_xy_inl(const Edge& E, float px, float py, int pid, float qx, float qy,
+                                                  int qid)
+{
+    const int s = area_cmp_exact_inl(E.ox, E.oy, E.ex, E.ey, px, py, qx, qy);
+    if (s != 0) return s > 0;
+    if (px == qx && py == qy) return pid < qid;
+    const bool p_first = (px < qx) || (px == qx && py < qy);
+    return E.fwd ? p_first : !p_first;
+}
+
+// settle_p without a call: the exact sign of an undecided orientation
+__device__ __forceinline__ void settle_inl(int& s, bool need, float ox, float oy, float ex, float ey, float px,
+                                           float py, uint32_t& n_exact)
+{
+    if (__ballot(need)) {
+        if (need) {
+            s = orient_exact_inl(ox, oy, ex, ey, px, py);
+            ++n_exact;
+        }
+    }
+}
+
+__device__ __forceinline__ bool fc_beats(const Edge& E, const FCand& P, const FCand& Q, bool fp64, uint32_t& n_exact)
+{
+    if (Q.id < 0) return P.id >= 0;
+    if (P.id < 0) return false;
+    if (!fp64) {
+        if (P.lo > Q.hi) return true;
+        if (Q.lo > P.hi) return false;
+    }
+    ++n_exact;
+    return beats_exact_xy(E, P.x, P.y, P.id, Q.x, Q.y, Q.id);
+}
+
+// Offer point (px, py, id) with interval [lo, hi] to the lane's candidate q
+// when m holds. Undecided comparisons fetch q's coordinates from the input.
+__device__ __forceinline__ void lc_offer(LCand& q, bool m, float lo, float hi, int id, float px, float py,
+                                         const Edge& E, const float2* xy, bool fp64, uint32_t& n_exact)
+{
+    // an empty q loses to any point; NaN bounds (overflow) leave the
+    // comparison undecided, as does the float64-only mode
+    const bool win0 = m && (q.id < 0 || (!fp64 && lo > q.hi));
+    const bool und = m && !win0 && (fp64 || !(q.lo > hi));
+    bool win = win0;
+    if (__ballot(und)) {
+        if (und) {
+            const float2 Q = gld(xy + q.id);
+            ++n_exact;
+            win = beats_exact_xy_inl(E, px, py, id, Q.x, Q.y, q.id);
+        }
+    }
+    if (win) {
+        q.lo = lo; q.hi = hi; q.id = id;
+    }
+}
+
+// Filter-only offer: takes the point when its interval proves it farther;
+// returns true when only the exact order can decide (q is then unchanged).
+// (bitwise logic throughout: short-circuit operators would become branches)
+__device__ __forceinline__ bool lc_offer_fast(LCand& q, bool m, float lo, float hi, int id, bool fp64)
+{
+    const bool win = m & ((q.id < 0) | (!fp64 & (lo > q.hi)));
+    const bool und = m & !win & (fp64 | !(q.lo > hi));
+    q.lo = win ? lo : q.lo;
+    q.hi = win ? hi : q.hi;
+    q.id = win ? id : q.id;
+    return und;
+}
+
+// fast_sign without branches
+__device__ __forceinline__ int fsign(const Orient32& o, bool fp64)
+{
+    const bool ok = !fp64 & (fabsf(o.d) > o.es);
+    return ok ? (o.d > 0.0f ? 1 : -1) : 0;
+}
+
+__device__ __forceinline__ FCand lc_full(const LCand& q, const float2* xy)
+{
+    FCand c = fc_none();
+    if (q.id >= 0) {
+        const float2 p = gld(xy + q.id);
+        c.lo = q.lo; c.hi = q.hi; c.x = p.x; c.y = p.y; c.id = q.id;
+    }
+    return c;
+}
+
+__device__ __forceinline__ FCand shfl_xor_fc(const FCand& c, int m)
+{
+    FCand r;
+    r.lo = __shfl_xor(c.lo, m); r.hi = __shfl_xor(c.hi, m);
+    r.x = __shfl_xor(c.x, m); r.y = __shfl_xor(c.y, m);
+    r.id = __shfl_xor(c.id, m);
+    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    return r;
+}
+
+__device__ __forceinline__ FCand wave_max_fc(const Edge& E, FCand v, bool fp64, uint32_t& n_exact)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const FCand o = shfl_xor_fc(v, m);
+        // a total order: both lanes of a pair keep the same winner
+        if (fc_beats(E, o, v, fp64, n_exact)) v = o;
+    }
+    return v;
+}
+
+// Block-wide farthest point (result valid on every thread). `lds` holds kWaves entries.
+__device__ __forceinline__ FCand block_max_fc(const Edge& E, FCand v, FCand* lds, bool fp64, uint32_t& n_exact)
+{
+    const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+    v = wave_max_fc(E, v, fp64, n_exact);
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    FCand r = lds[lane & (kWaves - 1)];
+#pragma unroll
+    for (int m = 1; m < kWaves; m <<= 1) {
+        const FCand o = shfl_xor_fc(r, m);
+        if (fc_beats(E, o, r, fp64, n_exact)) r = o;
+    }
+    return r;  // lanes 0..15 of every wave agree; lane 0's is used
+}
+
+// Lexicographic extreme with the lowest index among coincident points.
+struct Lex {
+    float x, y;
+    int id;
+};
+__device__ __forceinline__ bool lex_beats(bool mx, const Lex& P, const Lex& Q)
+{
+    const bool less = (P.x < Q.x) | ((P.x == Q.x) & (P.y < Q.y));
+    const bool more = (P.x > Q.x) | ((P.x == Q.x) & (P.y > Q.y));
+    const bool eq = (P.x == Q.x) & (P.y == Q.y);
+    return (mx ? more : less) | (eq & (P.id < Q.id));
+}
+__device__ __forceinline__ Lex shfl_xor_lex(const Lex& c, int m)
+{
+    Lex r;
+    r.x = __shfl_xor(c.x, m); r.y = __shfl_xor(c.y, m); r.id = __shfl_xor(c.id, m);
+    return r;
+}
+
+struct SeedPart {
+    float mnx, mny;
+    int mni;
+    float mxx, mxy;
+    int mxi;
+    int bad;
+    int pad;
+};
+
+struct SplitPart {
+    int cnt[4];
+    FCand c[2];
+};
+
+struct FirstPart {
+    FCand c[4];
+};
+
+// Per-call state of the streaming path in the workspace.
+struct StreamWs {
+    SeedPart seed[kMaxChunks];
+    SplitPart split[kMaxChunks];
+    FirstPart first[kMaxChunks];
+    SeedPart seed_res;    // A (mn*), B (mx*), non-finite flag
+    SplitPart split_res;  // n_lo, n_up, C_lo, C_up
+    unsigned int done[4];   // workgroups finished: seed, split, first compaction
+    unsigned int pad[60];
+    unsigned int cursor[4]; // first compaction: points placed so far in each child
+    unsigned int pad2[60];
+    // followed by one 64-bit count word per tile (spare)
+};
+__device__ __forceinline__ uint64_t* stream_slots(void* ws) { return reinterpret_cast<uint64_t*>(static_cast<StreamWs*>(ws) + 1); }
+
+// the pairs of one wave's rows in tile j: pair index of row r, lane l is
+// p0 + 64 r + l
+__device__ __forceinline__ int tile_pair0(int j, int w) { return j * kSTilePairs + w * (kSRows * 64); }
+
+// Loads pair p (points 2p and 2p + 1; npf full pairs, plus one point if
+// odd). Point 2p + h exists iff 2p + h < n.
+__device__ __forceinline__ float4 load_pair(const float2* xy, int npf, int odd, int p)
+{
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (p < npf) {
+        v = gld(reinterpret_cast<const float4*>(xy) + p);
+    } else if (odd && p == npf) {
+        const float2 t = gld(xy + 2 * p);
+        v.x = t.x; v.y = t.y;
+    }
+    return v;
+}
+
+// Points this lane holds in its wave's rows of a tile (pairs p0 + 64 r).
+__device__ __forceinline__ uint32_t lane_points(int n, int p0, int wave_p0)
+{
+    if (2 * (wave_p0 + 64 * kSRows) <= n) return 2 * kSRows;  // the wave's rows are full
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < kSRows; ++r) c += (uint32_t)min(max(n - 2 * (p0 + 64 * r), 0), 2);
+    return c;
+}
+
+// Loads this lane's pairs p0 + 64 r of one wave's rows (first pair
+// wave_p0): unguarded 16-byte loads when every point exists, so that all
+// loads are in flight together.
+__device__ __forceinline__ void load_rows(const float2* xy, int n, int p0, int wave_p0, float4 (&v)[kSRows])
+{
+    if (2 * (wave_p0 + 64 * kSRows) <= n) {
+        const float4* x4 = reinterpret_cast<const float4*>(xy) + p0;
+#pragma unroll
+        for (int r = 0; r < kSRows; ++r) v[r] = gld(x4 + 64 * r);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kSRows; ++r) v[r] = load_pair(xy, n >> 1, n & 1, p0 + 64 * r);
+    }
+}
+
+// One 64-bit word per tile: bit 63 marks it written, four 15-bit counts.
+__device__ __forceinline__ uint64_t pack_counts(const int (&c)[4])
+{
+    return (1ull << 63) | (uint64_t)c[0] | ((uint64_t)c[1] << 15) | ((uint64_t)c[2] << 30) | ((uint64_t)c[3] << 45);
+}
+__device__ __forceinline__ void unpack_counts(uint64_t v, int (&c)[4])
+{
+    c[0] = (int)(v & 0x7fff); c[1] = (int)((v >> 15) & 0x7fff);
+    c[2] = (int)((v >> 30) & 0x7fff); c[3] = (int)((v >> 45) & 0x7fff);
+}
+
+// set bits of M below this lane
+__device__ __forceinline__ int lanes_below(uint64_t M)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Lower side (strictly right of A->B): edges A->C_lo (bucket 0) and C_lo->B
+// (bucket 1); upper side: B->C_up (2) and C_up->A (3). Section 4.4.3 keeps
+// a point for the child whose edge it is strictly right of (the paper's
+// "and" reads "or": with an exact farthest point no point is right of both).
+struct FirstGeo {
+    float ax, ay, bx, by, lx, ly, ux, uy;
+};
+
+// Filter-only classification: 0..3, 7 (no child), or 15 when a sign needs
+// the exact path.
+__device__ __forceinline__ int first_fast(const FirstGeo& g, float x, float y, bool valid, bool fp64, float& a,
+                                          float& w)
+{
+    const Orient32 o = orient32p(g.ax, g.ay, g.bx, g.by, x, y);
+    const int side = fsign(o, fp64);
+    const bool up = side > 0;
+    const float sx = up ? g.bx : g.ax, sy = up ? g.by : g.ay;
+    const float mx = up ? g.ux : g.lx, my = up ? g.uy : g.ly;
+    const float tx = up ? g.ax : g.bx, ty = up ? g.ay : g.by;
+    const Orient32 o1 = orient32p(sx, sy, mx, my, x, y);
+    const Orient32 o2 = orient32p(mx, my, tx, ty, x, y);
+    const int s1 = fsign(o1, fp64), s2 = fsign(o2, fp64);
+    const bool in1 = s1 < 0, in2 = !in1 & (s2 < 0);
+    a = -(in1 ? o1.d : o2.d);
+    w = 2.0f * (in1 ? o1.es : o2.es);
+    const int b = up ? 2 : 0;
+    // undecided: the side, or the first edge's sign, or (first edge not
+    // outside) the second edge's sign
+    const bool und = (side == 0) | (s1 == 0) | ((s1 > 0) & (s2 == 0));
+    return !valid ? 7 : (und ? 15 : (in1 ? b : (in2 ? b + 1 : 7)));
+}
+
+__device__ __forceinline__ int first_classify(const FirstGeo& g, float x, float y, bool valid, bool fp64, float& a,
+                                              float& w, Counters& ctr)
+{
+    ctr.orient += valid ? 3 : 0;
+    const Orient32 o = orient32p(g.ax, g.ay, g.bx, g.by, x, y);
+    int side = fast_sign(o, fp64);
+    settle_inl(side, valid && side == 0, g.ax, g.ay, g.bx, g.by, x, y, ctr.orient_exact);
+    const bool up = side > 0;
+    const float sx = up ? g.bx : g.ax, sy = up ? g.by : g.ay;  // first edge's start
+    const float mx = up ? g.ux : g.lx, my = up ? g.uy : g.ly;  // apex
+    const float tx = up ? g.ax : g.bx, ty = up ? g.ay : g.by;  // second edge's end
+    const Orient32 o1 = orient32p(sx, sy, mx, my, x, y);
+    const Orient32 o2 = orient32p(mx, my, tx, ty, x, y);
+    int s1 = fast_sign(o1, fp64), s2 = fast_sign(o2, fp64);
+    const bool live = valid && side != 0;
+    settle_inl(s1, live && s1 == 0, sx, sy, mx, my, x, y, ctr.orient_exact);
+    settle_inl(s2, live && s1 >= 0 && s2 == 0, mx, my, tx, ty, x, y, ctr.orient_exact);
+    const bool in1 = s1 < 0, in2 = !in1 && s2 < 0;
+    a = -(in1 ? o1.d : o2.d);
+    w = 2.0f * (in1 ? o1.es : o2.es);
+    const int b = up ? 2 : 0;
+    return !live ? 7 : (in1 ? b : (in2 ? b + 1 : 7));
+}
+
+__device__ __forceinline__ bool spin_word(const uint64_t* p, uint64_t& v, int* err)
+{
+    int spins = 0;
+    while (!((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
+        if (++spins > kSpinLimit) {
+            atomicOr(err, kErrSpin);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// Timestamp by any one thread (the streaming kernels' phase ends are seen by
+// whichever workgroup finishes last).
+__device__ __forceinline__ void stamp_here(const HullArgs& a, int tag)
+{
+    if (a.timing) {
+        const int k = a.info->nstamps;
+        if (k < kMaxStamps) {
+            a.info->stamp[k] = wall_clock64();
+            a.info->stamp_tag[k] = tag;
+            a.info->nstamps = k + 1;
+        }
+    }
+}
+
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// True on the workgroup that arrives last at counter *ctr (nb arrivals), after
+// it has acquired every earlier arrival's writes.
+__device__ __forceinline__ bool last_arrival(unsigned int* ctr, int nb)
+{
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int k = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = k == (unsigned int)nb - 1u;
+        if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+// ---- cold code: reductions (out of line, called where little is live) and
+// the exact settling of the few points the filter leaves open (inline, one
+// copy, run only by waves that have such a point)
+
+// Block-wide farthest point for edge o -> e (every thread gets it).
+__device__ __noinline__ FCand block_max_call(float ox, float oy, float ex, float ey, FCand v, int fp64)
+{
+    __shared__ FCand lds[kWaves];
+    const Edge E = make_edge(ox, oy, ex, ey);
+    uint32_t n = 0;
+    return block_max_fc(E, v, lds, fp64 != 0, n);
+}
+
+// Lane state of the split and its exact settling.
+struct SplitLane {
+    LCand q0, q1;
+    int c0, c1;
+    uint32_t n_orient_exact, n_cmp_exact;
+};
+
+// Points (bit i of pend: row i / 2, point i % 2 of pairs p0 + 64 r) whose side
+// or farthest-point comparison the filter left open.
+__device__ __forceinline__ void split_pending(SplitLane* st, uint32_t pend, int p0, float ax, float ay, float bx,
+                                           float by, const float2* xy, int fp64)
+{
+    const bool f64 = fp64 != 0;
+    const Edge eab = make_edge(ax, ay, bx, by), eba = make_edge(bx, by, ax, ay);
+    SplitLane s = *st;
+#pragma unroll 1
+    for (int i = 0; i < 2 * kSRows; ++i) {
+        const bool mine = (pend >> i) & 1u;
+        if (!__ballot(mine)) continue;
+        if (mine) {
+            const int id = 2 * (p0 + 64 * (i >> 1)) + (i & 1);
+            const float2 P = gld(xy + id);
+            const Orient32 o = orient32p(ax, ay, bx, by, P.x, P.y);
+            const int f = fast_sign(o, f64);
+            int sg = f;
+            if (sg == 0) {
+                sg = orient_exact_inl(ax, ay, bx, by, P.x, P.y);
+                ++s.n_orient_exact;
+            }
+            const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
+            const float lo = ar - wr, hi = ar + wr;
+            const bool lower = sg < 0, upper = sg > 0;
+            // the fast pass counted the point iff its side was certified
+            if (f == 0) {
+                s.c0 += lower ? 1 : 0;
+                s.c1 += upper ? 1 : 0;
+            }
+            lc_offer(s.q0, lower, lo, hi, id, P.x, P.y, eab, xy, f64, s.n_cmp_exact);
+            lc_offer(s.q1, upper, lo, hi, id, P.x, P.y, eba, xy, f64, s.n_cmp_exact);
+        }
+    }
+    *st = s;
+}
+
+struct FirstLane {
+    LCand q[4];
+    uint32_t code_lo, code_hi;
+    uint32_t n_orient_exact, n_cmp_exact;
+};
+
+__device__ __forceinline__ void first_pending(FirstLane* st, uint32_t pend, int p0, FirstGeo g, const float2* xy,
+                                           int fp64)
+{
+    const bool f64 = fp64 != 0;
+    Edge E[4];
+    E[0] = make_edge(g.ax, g.ay, g.lx, g.ly);
+    E[1] = make_edge(g.lx, g.ly, g.bx, g.by);
+    E[2] = make_edge(g.bx, g.by, g.ux, g.uy);
+    E[3] = make_edge(g.ux, g.uy, g.ax, g.ay);
+    FirstLane s = *st;
+#pragma unroll 1
+    for (int i = 0; i < 2 * kSRows; ++i) {
+        const bool mine = (pend >> i) & 1u;
+        if (!__ballot(mine)) continue;
+        if (mine) {
+            const int id = 2 * (p0 + 64 * (i >> 1)) + (i & 1);
+            const float2 P = gld(xy + id);
+            float ar, wr;
+            Counters c = {0u, s.n_orient_exact, 0u};
+            const int code = first_classify(g, P.x, P.y, true, f64, ar, wr, c);
+            s.n_orient_exact = c.orient_exact;
+            const float lo = ar - wr, hi = ar + wr;
+            // the fast pass offered nothing for a pending point
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lc_offer(s.q[k], code == k, lo, hi, id, P.x, P.y, E[k], xy, f64, s.n_cmp_exact);
+            const int sh = 4 * (i & 7);
+            if (i < 8) s.code_lo = (s.code_lo & ~(15u << sh)) | ((uint32_t)code << sh);
+            else s.code_hi = (s.code_hi & ~(15u << sh)) | ((uint32_t)code << sh);
+        }
+    }
+    *st = s;
+}
+
+// Workgroup partial of the split: side counts and farthest points.
+__device__ __forceinline__ void split_wg_partial(SplitPart* out, SplitLane s, float ax, float ay, float bx, float by,
+                                              const float2* xy, int fp64)
+{
+    __shared__ int cnt[kWaves][2];
+    const int lane = lane_id(), w = wave_index();
+    const int c0 = wave_sum(s.c0), c1 = wave_sum(s.c1);
+    if (lane == 0) { cnt[w][0] = c0; cnt[w][1] = c1; }
+    const FCand f0 = block_max_call(ax, ay, bx, by, lc_full(s.q0, xy), fp64);
+    const FCand f1 = block_max_call(bx, by, ax, ay, lc_full(s.q1, xy), fp64);
+    if (threadIdx.x == 0) {
+        SplitPart sp;
+        sp.cnt[0] = 0; sp.cnt[1] = 0; sp.cnt[2] = 0; sp.cnt[3] = 0;
+        for (int u = 0; u < kWaves; ++u) { sp.cnt[0] += cnt[u][0]; sp.cnt[1] += cnt[u][1]; }
+        sp.c[0] = f0;
+        sp.c[1] = f1;
+        gst(out, sp);
+    }
+}
+
+// The last workgroup of the seed: A, B and the non-finite flag.
+__device__ __forceinline__ void seed_finish(const HullArgs& a)
+{
+    __shared__ Lex s_lex[2][kWaves];
+    __shared__ int s_bad[kWaves];
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index(), nb = (int)gridDim.x;
+    Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
+    int bad = 0;
+    if (t < nb) {
+        const SeedPart sp = gld(&ws->seed[t]);
+        mn.x = sp.mnx; mn.y = sp.mny; mn.id = sp.mni;
+        mx.x = sp.mxx; mx.y = sp.mxy; mx.id = sp.mxi;
+        bad = sp.bad;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Lex o0 = shfl_xor_lex(mn, m), o1 = shfl_xor_lex(mx, m);
+        if (lex_beats(false, o0, mn)) mn = o0;
+        if (lex_beats(true, o1, mx)) mx = o1;
+        bad |= __shfl_xor(bad, m);
+    }
+    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = bad; }
+    __syncthreads();
+    if (t == 0) {
+        Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
+        int qb = s_bad[0];
+        for (int u = 1; u < kWaves; ++u) {
+            if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
+            if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
+            qb |= s_bad[u];
+        }
+        SeedPart r;
+        r.mnx = q0.x; r.mny = q0.y; r.mni = q0.id;
+        r.mxx = q1.x; r.mxy = q1.y; r.mxi = q1.id;
+        r.bad = qb; r.pad = 0;
+        gst(&ws->seed_res, r);
+        if (qb) atomicOr(a.err, kErrNonFinite);
+        SetInfo si = {};
+        si.ax = q0.x; si.ay = q0.y; si.aid = q0.id;
+        si.bx = q1.x; si.by = q1.y; si.bid = q1.id;
+        gst(a.sets, si);
+        if (!qb && q0.x == q1.x && q0.y == q1.y) {
+            // every point sits at one position: the hull is its lowest index
+            record_vertex(a.bitmap, a.vidx, a.vlist, a.info, 0, q0.id);
+            a.sv[0] = 0;
+            a.sv[1] = 0;
+            a.vstart[0][0] = 0;
+        }
+        stamp_here(a, 1);
+    }
+}
+
+// The last workgroup of the split: side counts and farthest points over all
+// workgroups, the vertex keys of A and B.
+__device__ __forceinline__ void split_finish(const HullArgs& a, float ax, float ay, float bx, float by, int aid, int bid)
+{
+    __shared__ int cnt[kWaves][2];
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index(), nb = (int)gridDim.x;
+    int c0 = 0, c1 = 0;
+    FCand f0 = fc_none(), f1 = fc_none();
+    if (t < nb) {
+        c0 = gld(&ws->split[t].cnt[0]);
+        c1 = gld(&ws->split[t].cnt[1]);
+        f0 = gld(&ws->split[t].c[0]);
+        f1 = gld(&ws->split[t].c[1]);
+    }
+    c0 = wave_sum(c0);
+    c1 = wave_sum(c1);
+    if (lane == 0) { cnt[w][0] = c0; cnt[w][1] = c1; }
+    f0 = block_max_call(ax, ay, bx, by, f0, a.fp64);
+    f1 = block_max_call(bx, by, ax, ay, f1, a.fp64);
+    if (t == 0) {
+        int n_lo = 0, n_up = 0;
+        for (int u = 0; u < kWaves; ++u) { n_lo += cnt[u][0]; n_up += cnt[u][1]; }
+        SplitPart r;
+        r.cnt[0] = n_lo; r.cnt[1] = n_up; r.cnt[2] = 0; r.cnt[3] = 0;
+        r.c[0] = f0;
+        r.c[1] = f1;
+        gst(&ws->split_res, r);
+        // vertex keys: A at the first slot, B right after the lower side
+        record_vertex(a.bitmap, a.vidx, a.vlist, a.info, 0, aid);
+        record_vertex(a.bitmap, a.vidx, a.vlist, a.info, 1 + n_lo, bid);
+        SetInfo si = gld(a.sets);
+        si.n_lo = n_lo; si.n_up = n_up;
+        si.clx = f0.x; si.cly = f0.y; si.clid = f0.id;
+        si.cux = f1.x; si.cuy = f1.y; si.cuid = f1.id;
+        gst(a.sets, si);
+        if (n_lo == 0 && n_up == 0) {
+            // collinear input: the hull is [A, B]
+            a.sv[0] = 0;
+            a.sv[1] = 0;
+            a.vstart[0][0] = 0;
+        }
+        stamp_here(a, 2);
+    }
+}
+
+// Workgroup partial of the first compaction (farthest point of each child).
+__device__ __forceinline__ void first_wg_partial(FirstPart* out, FirstLane s, FirstGeo g, const float2* xy, int fp64)
+{
+    FirstPart fp;
+    fp.c[0] = block_max_call(g.ax, g.ay, g.lx, g.ly, lc_full(s.q[0], xy), fp64);
+    fp.c[1] = block_max_call(g.lx, g.ly, g.bx, g.by, lc_full(s.q[1], xy), fp64);
+    fp.c[2] = block_max_call(g.bx, g.by, g.ux, g.uy, lc_full(s.q[2], xy), fp64);
+    fp.c[3] = block_max_call(g.ux, g.uy, g.ax, g.ay, lc_full(s.q[3], xy), fp64);
+    if (threadIdx.x == 0) gst(out, fp);
+}
+
+// The last workgroup of the first compaction: the farthest point of each child
+// over all workgroups, the children as the first pass's segment table
+// (sections 4.4.2 / 4.4.4), and the ring keys of C_lo and C_up.
+__device__ __forceinline__ void first_finish(const HullArgs& a, FirstGeo g, int n_lo, int n_up, int clid, int cuid, int cnt0,
+                                          int cnt1, int cnt2, int cnt3)
+{
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    const int t = (int)threadIdx.x, nb = (int)gridDim.x;
+    const float ex[5] = {g.ax, g.lx, g.bx, g.ux, g.ax}, ey[5] = {g.ay, g.ly, g.by, g.uy, g.ay};
+    FCand C[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        FCand f = fc_none();
+        if (t < nb) f = gld(&ws->first[t].c[k]);
+        C[k] = block_max_call(ex[k], ey[k], ex[k + 1], ey[k + 1], f, a.fp64);
+    }
+    if (t == 0) {
+        const int cnt[4] = {cnt0, cnt1, cnt2, cnt3};
+        if (n_lo > 0) record_vertex(a.bitmap, a.vidx, a.vlist, a.info, 1 + cnt0, clid);
+        if (n_up > 0) record_vertex(a.bitmap, a.vidx, a.vlist, a.info, 2 + n_lo + cnt2, cuid);
+        const int off[4] = {1, 1 + n_lo - cnt1, 2 + n_lo, 2 + n_lo + n_up - cnt3};
+        int S = 0, V = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (cnt[k] <= 0) continue;
+            Seg sg;
+            sg.ax = ex[k]; sg.ay = ey[k]; sg.bx = ex[k + 1]; sg.by = ey[k + 1];
+            sg.cx = C[k].x; sg.cy = C[k].y;
+            sg.off = off[k];
+            sg.len = cnt[k];
+            gst(a.segs[0] + S, sg);
+            a.seg_cid[0][S] = C[k].id;
+            a.vstart[0][S] = V;
+            ++S;
+            V += cnt[k];
+        }
+        a.vstart[0][S] = V;
+        a.sv[0] = S;
+        a.sv[1] = V;
+        stamp_here(a, 3);
+    }
+}
+
+// ==================================================================== seed
+// Lexicographic minimum and maximum of the input (section 4.3: the leftmost
+// and rightmost points; coincident points: the lowest index) and the
+// non-finite check.
+__global__ __launch_bounds__(kBlock) void k_sseed(HullArgs a)
+{
+    __shared__ Lex s_lex[2][kWaves];
+    __shared__ int s_bad[kWaves];
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
+    const int n = a.N;
+    const int ntiles = (n + kSTile - 1) / kSTile;
+    const float2* xy = a.xy;
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    if (b == 0 && t == 0) stamp_here(a, 0);
+    Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
+    bool bad = false;
+    for (int j = b; j < ntiles; j += nb) {
+        const int p0 = tile_pair0(j, w) + lane;
+        float4 v[kSRows];
+        load_rows(xy, n, p0, tile_pair0(j, w), v);
+#pragma unroll
+        for (int r = 0; r < kSRows; ++r) {
+            const int id0 = 2 * (p0 + 64 * r);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
+                const bool m = id0 + h < n;
+                bad |= m & !(isfinite(x) & isfinite(y));
+                // a lane sees its points in increasing index order: strict
+                // comparisons keep the lowest index among coincident points
+                const bool lt = m & ((x < mn.x) | ((x == mn.x) & (y < mn.y)));
+                const bool gt = m & ((x > mx.x) | ((x == mx.x) & (y > mx.y)));
+                mn.x = lt ? x : mn.x; mn.y = lt ? y : mn.y; mn.id = lt ? id0 + h : mn.id;
+                mx.x = gt ? x : mx.x; mx.y = gt ? y : mx.y; mx.id = gt ? id0 + h : mx.id;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Lex o0 = shfl_xor_lex(mn, m), o1 = shfl_xor_lex(mx, m);
+        if (lex_beats(false, o0, mn)) mn = o0;
+        if (lex_beats(true, o1, mx)) mx = o1;
+    }
+    const int any_bad = __ballot(bad) != 0ull;
+    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = any_bad; }
+    __syncthreads();
+    if (t == 0) {
+        Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
+        int qb = s_bad[0];
+        for (int u = 1; u < kWaves; ++u) {
+            if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
+            if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
+            qb |= s_bad[u];
+        }
+        SeedPart sp;
+        sp.mnx = q0.x; sp.mny = q0.y; sp.mni = q0.id;
+        sp.mxx = q1.x; sp.mxy = q1.y; sp.mxi = q1.id;
+        sp.bad = qb; sp.pad = 0;
+        gst(&ws->seed[b], sp);
+    }
+    // clear the first compaction's child cursors (used after this kernel)
+    if (b == 0 && t < 4) ws->cursor[t] = 0u;
+    if (last_arrival(&ws->done[0], nb)) seed_finish(a);
+}
+
+// =================================================================== split
+// Side of every point w.r.t. the line A->B (section 4.3) and the farthest
+// point of each side (section 4.4.1). Points on the line belong to neither
+// side.
+__global__ __launch_bounds__(kBlock) void k_ssplit(HullArgs a)
+{
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int lane = lane_id(), w = wave_index();
+    const int fp64 = a.fp64;
+    const int n = a.N;
+    const int ntiles = (n + kSTile - 1) / kSTile;
+    const float2* xy = a.xy;
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    const SeedPart sr = gld(&ws->seed_res);
+    if (sr.bad || (sr.mnx == sr.mxx && sr.mny == sr.mxy)) return;  // finished by the seed
+    const float ax = sr.mnx, ay = sr.mny, bx = sr.mxx, by = sr.mxy;
+    SplitLane s;
+    s.q0 = lc_none(); s.q1 = lc_none();
+    s.c0 = 0; s.c1 = 0;
+    s.n_orient_exact = 0u; s.n_cmp_exact = 0u;
+    uint32_t n_orient = 0u;
+    for (int j = b; j < ntiles; j += nb) {
+        const int p0 = tile_pair0(j, w) + lane;
+        float4 v[kSRows];
+        load_rows(xy, n, p0, tile_pair0(j, w), v);
+        // filter-only pass; points needing an exact decision are settled
+        // afterwards, out of line
+        uint32_t pend = 0u;
+#pragma unroll
+        for (int r = 0; r < kSRows; ++r) {
+            const int id0 = 2 * (p0 + 64 * r);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
+                const bool m = id0 + h < n;
+                const Orient32 o = orient32p(ax, ay, bx, by, x, y);
+                const int sg = fsign(o, fp64 != 0);
+                // lower side: the area for A->B is -orient; upper: for B->A it is orient
+                const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
+                const float lo = ar - wr, hi = ar + wr;
+                const bool lower = m & (sg < 0), upper = m & (sg > 0);
+                const bool u0 = lc_offer_fast(s.q0, lower, lo, hi, id0 + h, fp64 != 0);
+                const bool u1 = lc_offer_fast(s.q1, upper, lo, hi, id0 + h, fp64 != 0);
+                s.c0 += lower ? 1 : 0;
+                s.c1 += upper ? 1 : 0;
+                pend |= (uint32_t)((m & (sg == 0)) | u0 | u1) << (2 * r + h);
+            }
+        }
+        n_orient += lane_points(n, p0, tile_pair0(j, w));
+        if (__ballot(pend != 0u)) {
+            SplitLane tmp = s;
+            split_pending(&tmp, pend, p0, ax, ay, bx, by, xy, fp64);
+            s = tmp;
+        }
+    }
+    split_wg_partial(&ws->split[b], s, ax, ay, bx, by, xy, fp64);
+    Counters ctr = {n_orient, s.n_orient_exact, s.n_cmp_exact};
+    flush_counters(a.stats, ctr);
+    if (last_arrival(&ws->done[1], nb)) split_finish(a, ax, ay, bx, by, sr.mni, sr.mxi);
+}
+
+// ======================================================== first compaction
+// Sections 4.4.2 - 4.4.4 on the two sides: every point of the lower side goes
+// to child (A, C_lo) or (C_lo, B), every point of the upper side to (B, C_up)
+// or (C_up, A), or is discarded; children are packed into the side's slots
+// from the front and the back; the farthest point of each child is found on
+// the way (the first pass's section 4.4.1). A tile reserves its children's
+// slots with one atomic add per child (no workgroup waits for another, so
+// this is an ordinary launch); the order of the points inside a child is
+// therefore that of the reservations, which no later step depends on (every
+// decision is geometric, with index tie-breaks). The last workgroup to finish
+// writes the first pass's segment table.
+__global__ __launch_bounds__(kBlock) void k_sfirst(HullArgs a)
+{
+    __shared__ int s_wcnt[kWaves][4];  // per-wave child counts of the current tile
+    __shared__ int s_wbase[kWaves][4]; // ... as offsets inside the tile's reservation
+    __shared__ int s_base[4];          // the tile's first rank in each child
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
+    const int fp64 = a.fp64;
+    const int n = a.N;
+    const int ntiles = (n + kSTile - 1) / kSTile;
+    const float2* xy = a.xy;
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    const SeedPart sr = gld(&ws->seed_res);
+    if (sr.bad || (sr.mnx == sr.mxx && sr.mny == sr.mxy)) return;  // finished by the seed
+    const SplitPart pr = gld(&ws->split_res);
+    const int n_lo = pr.cnt[0], n_up = pr.cnt[1];
+    if (n_lo == 0 && n_up == 0) return;  // finished by the split
+    FirstGeo g;
+    g.ax = sr.mnx; g.ay = sr.mny; g.bx = sr.mxx; g.by = sr.mxy;
+    g.lx = pr.c[0].x; g.ly = pr.c[0].y; g.ux = pr.c[1].x; g.uy = pr.c[1].y;
+    // output slot of rank R in child k: obase[k] + R (k even), obase[k] - R (k odd)
+    const int obase[4] = {1, n_lo, 2 + n_lo, 1 + n_lo + n_up};
+    FirstLane s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s.q[k] = lc_none();
+    s.n_orient_exact = 0u;
+    s.n_cmp_exact = 0u;
+    uint32_t n_orient = 0u;
+    float* X = a.X[0];
+    float* Y = a.Y[0];
+    int* I = a.I[0];
+    for (int j = b; j < ntiles; j += nb) {
+        const int p0 = tile_pair0(j, w) + lane;
+        s.code_lo = 0u;
+        s.code_hi = 0u;  // 4 bits per point i = 2 row + h: rows 0-3 / 4-7
+        {
+            // (the tile is loaded twice: here, and for the scatter once its
+            // slots are reserved, when it is still in the L2 cache; holding
+            // it in registers across the reservation would spill)
+            float4 v[kSRows];
+            load_rows(xy, n, p0, tile_pair0(j, w), v);
+            // filter-only pass; points needing an exact decision are settled
+            // afterwards, one at a time
+            uint32_t pend = 0u;
+#pragma unroll
+            for (int rr = 0; rr < kSRows; ++rr) {
+                const int id0 = 2 * (p0 + 64 * rr);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
+                    const bool m = id0 + h < n;
+                    float ar, wr;
+                    int code = first_fast(g, x, y, m, fp64 != 0, ar, wr);
+                    const float lo = ar - wr, hi = ar + wr;
+                    bool und = code == 15;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) und |= lc_offer_fast(s.q[k], code == k, lo, hi, id0 + h, fp64 != 0);
+                    code = und ? 15 : code;
+                    pend |= (uint32_t)und << (2 * rr + h);
+                    const int sh = 4 * (2 * (rr & 3) + h);
+                    if (rr < 4) s.code_lo |= (uint32_t)code << sh;
+                    else s.code_hi |= (uint32_t)code << sh;
+                }
+            }
+            n_orient += 3u * lane_points(n, p0, tile_pair0(j, w));
+            if (__ballot(pend != 0u)) {
+                FirstLane tmp = s;
+                first_pending(&tmp, pend, p0, g, xy, fp64);
+                s = tmp;
+            }
+        }
+        int wc[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 2 * kSRows; ++i) {
+            const int sh = 4 * (i & 7);
+            const int code = (int)(((i < 8) ? s.code_lo : s.code_hi) >> sh) & 15;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wc[k] += __popcll(__ballot(code == k));
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_wcnt[w][k] = wc[k];
+        }
+        __syncthreads();
+        if (t < 4) {
+            // per-wave offsets inside the tile, and the tile's reservation
+            int run = 0;
+            for (int u = 0; u < kWaves; ++u) {
+                s_wbase[u][t] = run;
+                run += s_wcnt[u][t];
+            }
+            s_base[t] = run > 0 ? (int)atomicAdd(&ws->cursor[t], (unsigned int)run) : 0;
+        }
+        __syncthreads();
+        {
+            // scatter: ranks inside a row from ballots, so that each row
+            // writes one contiguous run per child
+            float4 v[kSRows];
+            load_rows(xy, n, p0, tile_pair0(j, w), v);
+            int run[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) run[k] = s_base[k] + s_wbase[w][k];
+#pragma unroll
+            for (int rr = 0; rr < kSRows; ++rr) {
+                const int id0 = 2 * (p0 + 64 * rr);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
+                    const int sh = 4 * (2 * (rr & 3) + h);
+                    const int code = (int)(((rr < 4) ? s.code_lo : s.code_hi) >> sh) & 15;
+                    int dst = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint64_t M = __ballot(code == k);
+                        const int rank = run[k] + lanes_below(M);
+                        const int d = (k & 1) ? obase[k] - rank : obase[k] + rank;
+                        dst = code == k ? d : dst;
+                        run[k] += __popcll(M);
+                    }
+                    if (code < 4) {
+                        gst(X + dst, x);
+                        gst(Y + dst, y);
+                        gst(I + dst, id0 + h);
+                    }
+                    // one point at a time: keeps the ballots of later points
+                    // from being hoisted (their masks would all be live)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    first_wg_partial(&ws->first[b], s, g, xy, fp64);
+    Counters ctr = {n_orient, s.n_orient_exact, s.n_cmp_exact};
+    flush_counters(a.stats, ctr);
+    if (last_arrival(&ws->done[2], nb)) {
+        const int c0 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[0]));
+        const int c1 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[1]));
+        const int c2 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[2]));
+        const int c3 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[3]));
+        first_finish(a, g, n_lo, n_up, pr.c[0].id, pr.c[1].id, c0, c1, c2, c3);
+    }
+}
+
+}  // namespace sqh

@@ -172,6 +172,22 @@ int sqh_hull(sqh_ctx *ctx, const float *d_xy, int64_t n, int32_t *d_out, int64_t
              int64_t *h_count, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
+ * sqh_hull without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). The library keeps one static scratch
+ * array per device (40 MiB, held until the process ends); the call allocates
+ * nothing. Arguments, result convention and return codes are those of
+ * sqh_hull, plus SQH_ENOMEM when n > SQH_NOALLOC_MAX_POINTS, and
+ * SQH_EDEVICE when the scratch array's device address could not be obtained
+ * by sqh_create. Every call on a device shares that device's array: calls
+ * that overlap on one device (several streams, threads or contexts) race
+ * and must be serialised by the caller. Synchronises the stream.
+ */
+#define SQH_NOALLOC_MAX_POINTS 262144
+int sqh_hull_noalloc(sqh_ctx *ctx, const float *d_xy, int64_t n, int32_t *d_out, int64_t out_cap,
+                     int64_t *h_count, void *stream);
+
+/*
  * Convex hulls of n_sets independent point sets stored back to back.
  *   d_xy       device, n_total (x, y) float32 pairs.
  *   d_set_off  device, n_sets + 1 int64, non-decreasing, d_set_off[0] = 0,

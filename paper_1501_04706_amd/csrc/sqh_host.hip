@@ -12,6 +12,7 @@
 #include <new>
 #include <vector>
 #include <deque>
+#include <mutex>
 
 #include "../../include/sqh.h"
 #include "sqh_kernels.hip"
@@ -92,6 +93,38 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
 }
 
 }  // namespace
+
+// ---- allocation-free entry point: a file-scope device scratch array ------
+//
+// sqh_hull_noalloc runs single hulls of at most SQH_NOALLOC_MAX_POINTS points
+// in this array instead of a caller workspace. In host code `g_scratch` only
+// names the symbol; its device address (one copy per device) is looked up
+// once per device with hipGetSymbolAddress while sqh_create has that device
+// current, and only that address is ever passed to kernels.
+constexpr size_t kScratchBytes = size_t(40) << 20;
+static __device__ __align__(256) unsigned char g_scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+    int rc = SQH_EDEVICE;
+};
+ScratchSlot g_scratch_slot[kMaxDevices];
+
+// Called with `device` current.
+void scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return;
+    ScratchSlot& s = g_scratch_slot[device];
+    std::call_once(s.once, [&s]() {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_scratch)) == hipSuccess && p) {
+            s.ptr = p;
+            s.rc = SQH_OK;
+        }
+    });
+}
 
 struct TuneEntry {
     int log2n;  // problem class: floor(log2(max(n_total, 1)))
@@ -579,6 +612,7 @@ int sqh_create(sqh_ctx** out, int device)
         return SQH_EDEVICE;
     }
     c->max_grid = std::min(kMaxGrid, per_cu * c->cus);
+    scratch_init(device);  // the device is current here
     {
         const char* t = getenv("SQH_TRACE");
         c->trace = t ? atoi(t) : 0;  // 1: seed and split, 2: first compaction and first pass
@@ -644,6 +678,21 @@ int sqh_hull(sqh_ctx* c, const float* d_xy, int64_t n, int32_t* d_out, int64_t o
     if (!c || !h_count || n < 0) return SQH_EINVAL;
     *h_count = 0;
     return run(c, d_xy, n, 1, nullptr, d_out, nullptr, out_cap, h_count, d_ws, ws_bytes,
+               static_cast<hipStream_t>(stream));
+}
+
+int sqh_hull_noalloc(sqh_ctx* c, const float* d_xy, int64_t n, int32_t* d_out, int64_t out_cap, int64_t* h_count,
+                     void* stream)
+{
+    if (!c || !h_count || n < 0) return SQH_EINVAL;
+    *h_count = 0;
+    if (n > SQH_NOALLOC_MAX_POINTS) return SQH_ENOMEM;
+    if (c->device < 0 || c->device >= kMaxDevices) return SQH_EDEVICE;
+    const ScratchSlot& sl = g_scratch_slot[c->device];
+    if (sl.rc != SQH_OK) return SQH_EDEVICE;
+    Layout L;
+    if (!make_layout(n, 1, L) || L.bytes > kScratchBytes) return SQH_ENOMEM;
+    return run(c, d_xy, n, 1, nullptr, d_out, nullptr, out_cap, h_count, sl.ptr, kScratchBytes,
                static_cast<hipStream_t>(stream));
 }
 

@@ -111,6 +111,8 @@ def load() -> ctypes.CDLL:
     lib.sqh_workspace_bytes.restype = ctypes.c_size_t
     lib.sqh_hull.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
     lib.sqh_hull.restype = c_int
+    lib.sqh_hull_noalloc.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp]
+    lib.sqh_hull_noalloc.restype = c_int
     lib.sqh_hull_batched.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, ctypes.POINTER(i64), vp,
                                      ctypes.c_size_t, vp]
     lib.sqh_hull_batched.restype = c_int
@@ -204,6 +206,16 @@ def sqh_hull(ctx: int, xy, n: int, out, out_cap: int, ws, ws_bytes: int, stream=
     rc = load().sqh_hull(ctx, _ptr(xy), n, _ptr(out), out_cap, ctypes.byref(h), _ptr(ws), ws_bytes,
                          _stream_handle(stream))
     return rc, h.value
+
+
+def sqh_hull_noalloc(ctx: int, xy, n: int, out, out_cap: int, stream=None):
+    """Returns (return code, h)."""
+    h = ctypes.c_int64(0)
+    rc = load().sqh_hull_noalloc(ctx, _ptr(xy), n, _ptr(out), out_cap, ctypes.byref(h), _stream_handle(stream))
+    return rc, h.value
+
+
+SQH_NOALLOC_MAX_POINTS = 262144
 
 
 def sqh_hull_batched(ctx: int, xy, set_off, n_sets: int, n_total: int, out, out_off, out_cap: int, ws,

@@ -24,6 +24,11 @@ using namespace sqh;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Streaming passes enqueued per call: at most kStreamPassLaunches (each does
+// nothing once the segment table no longer qualifies); a context enqueues one
+// more than the previous call of the same size class needed.
+constexpr int kStreamPassLaunches = 8;
+constexpr int kMaxLaunches = 12;
 constexpr int kMaxGrid = kMaxChunks;  // workgroups of the persistent kernel (upper bound)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -86,8 +91,9 @@ bool make_layout(int64_t N, int64_t nsets, Layout& L)
     // sorted-chain variant: bucket counts per workgroup and totals
     L.shist = take(sizeof(int) * (size_t)kSortBuckets * (size_t)kMaxGrid);
     L.stot = take(sizeof(int) * (size_t)kSortBuckets);
-    // streaming path of one large set: partial results and one count word per tile
-    L.sws = take(sizeof(StreamWs) + sizeof(uint64_t) * (size_t)((N + kSTile - 1) / kSTile + 64));
+    // streaming path of one large set: partial results and pass state
+    // (the streaming pass's records: one per tile of kPTile points and per segment)
+    L.sws = take(N >= kStreamMin ? sizeof(StreamWs) + sizeof(PassRec) * (size_t)(N / kPTile + kSPassMaxS + 2) : 0);
     L.bytes = o;
     return true;
 }
@@ -150,6 +156,8 @@ struct sqh_ctx {
     int prefilter = 0;    // SQH_PREFILTER_*
     int variant = 0;      // SQH_VARIANT_*
     int stream = 1;       // large single hulls take the streaming path (SQH_STREAM=0 turns it off)
+    int spass_used[64];   // per size class: streaming passes the last call ran (-1: none yet)
+    sqh_ctx() { for (int& v : spass_used) v = -1; }
 };
 
 struct sqh_graph {
@@ -254,12 +262,14 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.ids2 = static_cast<int*>(at(L.ids2));
     a.gs2 = static_cast<int*>(at(L.gs2));
     a.sws = at(L.sws);
-    a.sdone = static_cast<StreamWs*>(a.sws)->done;
+    a.sdone = N >= kStreamMin ? static_cast<StreamWs*>(a.sws)->done : nullptr;
     // one large set in plain mode, 16-byte aligned input: the streaming path
     a.stream = (ctx->stream && nsets == 1 && N >= kStreamMin && !a.prefilter && !a.sorted &&
                 (reinterpret_cast<uintptr_t>(d_xy) & 15u) == 0)
                    ? 1
                    : 0;
+    a.start = a.stream ? static_cast<StreamWs*>(a.sws)->state : nullptr;
+    a.spasses = kStreamPassLaunches;
     const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
     reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
     return SQH_OK;
@@ -270,48 +280,67 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
 // reads the pre-filter's subset only where the pre-filter runs), or for the
 // sorted-chain variant its first phases, k_sort and its passes.
 inline bool pre_runs(const HullArgs& a) { return a.prefilter && a.G == 1 && a.N > 0; }
-// coop[i] = 0: kernel i never waits for other workgroups (an ordinary
-// launch, which starts without the cooperative launch's queue round trip).
-inline int coop_launches(const HullArgs& a, const void* (&f)[4], int (&coop)[4])
+
+// One launch of a call: cooperative launches take `grid` workgroups of
+// kBlock threads; the streaming kernels, which never wait for another
+// workgroup, are ordinary launches of 2 * grid workgroups of kSBlock threads
+// (ordinary launches start without the cooperative launch's queue round trip).
+struct Launch {
+    const void* f;
+    int coop;
+};
+
+// The streaming path ends with k_stail; the passes kernel follows it in the
+// same sequence when `fallback` is set (graphs), else only when the hull is
+// not complete after it (sqh_hull checks the device's flag).
+inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fallback = true)
 {
     int n = 0;
-    for (int i = 0; i < 4; ++i) coop[i] = 1;
+    auto add = [&](const void* f, int coop) { L[n].f = f; L[n].coop = coop; ++n; };
     if (a.stream) {
-        coop[n] = 0;
-        f[n++] = reinterpret_cast<const void*>(k_sseed);
-        coop[n] = 0;
-        f[n++] = reinterpret_cast<const void*>(k_ssplit);
-        coop[n] = 0;
-        f[n++] = reinterpret_cast<const void*>(k_sfirst);
-        f[n++] = reinterpret_cast<const void*>(k_hull<kHullPasses>);
+        add(reinterpret_cast<const void*>(k_sseed), 0);
+        add(reinterpret_cast<const void*>(k_ssplit), 0);
+        add(reinterpret_cast<const void*>(k_sfirst), 0);
+        for (int i = 0; i < a.spasses; ++i) add(reinterpret_cast<const void*>(k_spass), 0);
+        add(reinterpret_cast<const void*>(k_stail), 0);
+        if (fallback) add(reinterpret_cast<const void*>(k_hull<kHullPasses>), 1);
         return n;
     }
-    if (pre_runs(a)) f[n++] = reinterpret_cast<const void*>(k_prefilter);
+    if (pre_runs(a)) add(reinterpret_cast<const void*>(k_prefilter), 1);
     if (a.sorted && a.G == 1) {
-        f[n++] = reinterpret_cast<const void*>(k_hull<kHullFirst>);
-        f[n++] = reinterpret_cast<const void*>(k_sort);
-        f[n++] = reinterpret_cast<const void*>(k_hull<kHullPasses>);
+        add(reinterpret_cast<const void*>(k_hull<kHullFirst>), 1);
+        add(reinterpret_cast<const void*>(k_sort), 1);
+        add(reinterpret_cast<const void*>(k_hull<kHullPasses>), 1);
     } else {
-        f[n++] = pre_runs(a) ? reinterpret_cast<const void*>(k_hull<kHullPre>)
-                             : reinterpret_cast<const void*>(k_hull<kHullPlain>);
+        add(pre_runs(a) ? reinterpret_cast<const void*>(k_hull<kHullPre>)
+                        : reinterpret_cast<const void*>(k_hull<kHullPlain>),
+            1);
     }
     return n;
 }
+inline dim3 launch_grid(const Launch& l, int grid)
+{
+    if (l.f == reinterpret_cast<const void*>(k_stail)) return dim3(1);
+    return dim3(l.coop ? grid : std::min(2 * grid, kMaxSGrid));
+}
+inline dim3 launch_block(const Launch& l)
+{
+    return dim3(l.coop || l.f == reinterpret_cast<const void*>(k_stail) ? kBlock : kSBlock);
+}
 
 // Enqueue the workspace reset and the cooperative launches, bracketed by events.
-int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st)
+int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st, bool fallback = true)
 {
     HIP_OK(hipEventRecord(ctx->ev0, st));
     k_reset<<<reset_grid, 256, 0, st>>>(a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
-    const void* f[4];
-    int coop[4];
-    const int nf = coop_launches(a, f, coop);
+    Launch L[kMaxLaunches];
+    const int nf = call_launches(a, L, fallback);
     for (int i = 0; i < nf; ++i) {
-        if (coop[i]) HIP_OK(hipLaunchCooperativeKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
-        else HIP_OK(hipLaunchKernel(f[i], dim3(grid), dim3(kBlock), argv, 0, st));
+        if (L[i].coop) HIP_OK(hipLaunchCooperativeKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
+        else HIP_OK(hipLaunchKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
     }
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
@@ -397,8 +426,26 @@ int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const i
     int reset_grid = 1;
     int rc = setup(ctx, d_xy, N, nsets, d_set_off, d_out, d_out_off, out_cap, d_ws, ws_bytes, tu, a, reset_grid);
     if (rc != SQH_OK) return rc;
-    rc = enqueue(ctx, a, reset_grid, tu.grid, st);
+    if (!a.stream) {
+        rc = enqueue(ctx, a, reset_grid, tu.grid, st);
+        if (rc != SQH_OK) return rc;
+        return collect(ctx, a, N, out_cap, h_total, st, true);
+    }
+    // streaming path: the passes kernel only if the streaming kernels left work
+    const int cls = std::min(log2_class(N), 63);
+    a.spasses = ctx->spass_used[cls] < 0 ? kStreamPassLaunches
+                                         : std::min(kStreamPassLaunches, ctx->spass_used[cls] + 1);
+    rc = enqueue(ctx, a, reset_grid, tu.grid, st, false);
     if (rc != SQH_OK) return rc;
+    rc = collect(ctx, a, N, out_cap, h_total, st, true);
+    const HullInfo& hi = *ctx->hinfo;
+    const bool done = hi.stream_done != 0 || *ctx->herr != 0;
+    ctx->spass_used[cls] = (done && hi.spass_n < a.spasses) ? hi.spass_n : kStreamPassLaunches;
+    if (done) return rc;
+    void* argv[] = {static_cast<void*>(&a)};
+    HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull<kHullPasses>), dim3(tu.grid),
+                                      dim3(kBlock), argv, 0, st));
+    HIP_OK(hipEventRecord(ctx->ev1, st));
     return collect(ctx, a, N, out_cap, h_total, st, true);
 }
 
@@ -598,9 +645,7 @@ int sqh_create(sqh_ctx** out, int device)
                               reinterpret_cast<const void*>(k_hull<kHullPre>),
                               reinterpret_cast<const void*>(k_hull<kHullFirst>),
                               reinterpret_cast<const void*>(k_hull<kHullPasses>),
-                              reinterpret_cast<const void*>(k_prefilter), reinterpret_cast<const void*>(k_sort),
-                              reinterpret_cast<const void*>(k_sseed), reinterpret_cast<const void*>(k_ssplit),
-                              reinterpret_cast<const void*>(k_sfirst)};
+                              reinterpret_cast<const void*>(k_prefilter), reinterpret_cast<const void*>(k_sort)};
         for (const void* f : coop) {
             int k = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, kBlock, 0) != hipSuccess) k = 0;
@@ -840,17 +885,16 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     hipGraphNode_t prev = nullptr;
     bool ok = hipGraphCreate(&g->graph, 0) == hipSuccess &&
               hipGraphAddKernelNode(&prev, g->graph, nullptr, 0, &kp) == hipSuccess;
-    const void* f[4];
-    int fcoop[4];
-    const int nf = coop_launches(g->args, f, fcoop);
+    Launch L[kMaxLaunches];
+    const int nf = call_launches(g->args, L);
     for (int i = 0; ok && i < nf; ++i) {
         hipKernelNodeParams hp = kp;
-        hp.func = const_cast<void*>(f[i]);
-        hp.gridDim = dim3(tu.grid);
-        hp.blockDim = dim3(kBlock);
+        hp.func = const_cast<void*>(L[i].f);
+        hp.gridDim = launch_grid(L[i], tu.grid);
+        hp.blockDim = launch_block(L[i]);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, g->graph, &prev, 1, &hp) == hipSuccess &&
-             (!fcoop[i] ||
+             (!L[i].coop ||
               hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &coop) == hipSuccess);
         prev = node;
     }

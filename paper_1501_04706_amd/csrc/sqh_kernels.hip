@@ -757,6 +757,8 @@ struct HullInfo {
     int keep_n;       // pre-filter: kept points appended so far
     int sort_n;       // sorted-chain variant: points sorted (-1: no sort)
     int sort_bad;     // sorted-chain variant: neighbours out of order after the sort
+    int stream_done;  // streaming path: the hull is complete before the passes kernel
+    int spass_n;      // streaming path: passes run by k_spass
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -824,7 +826,9 @@ struct HullArgs {
     // results and tile count words
     void* sws;
     unsigned int* sdone;     // the streaming kernels' completion counters (cleared by k_reset)
-    int stream;              // 1: the streaming kernels run the first phases, k_hull<kHullPasses> the rest
+    const int* start;        // null, or {survivor buffer, pass} where k_hull<kHullPasses> starts
+    int stream;
+    int spasses;             // streaming path: k_spass launches in this call              // 1: the streaming kernels run the first phases, k_hull<kHullPasses> the rest
 };
 
 
@@ -1586,6 +1590,12 @@ __global__ __launch_bounds__(kBlock) void k_hull(HullArgs a)
     if (MODE == kHullPasses) {
         // the first phases ran in an earlier launch; a rejected input ended there
         if (ld_flag(a.err) & (kErrNonFinite | kErrBounds)) goto done;
+        if (a.start) {
+            // earlier launches also ran passes, or finished the hull
+            if (ld_flag(&a.info->stream_done)) goto done;
+            cur = ld_flag(a.start) & 1;
+            pass = ld_flag(a.start + 1);
+        }
         goto passes;
     }
     if (MODE != kHullFirst && a.G == 1 && in_n <= kSmallInput) {
@@ -2086,6 +2096,8 @@ __global__ void k_reset(HullArgs a)
         a.info->keep_n = 0;
         a.info->sort_n = -1;
         a.info->sort_bad = 0;
+        a.info->stream_done = 0;
+        a.info->spass_n = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     if (a.stream && gtid < 4) a.sdone[gtid] = 0u;

@@ -31,8 +31,14 @@
 
 namespace sqh {
 
+// Workgroups of 512 threads, two or more per compute unit, so that one
+// workgroup's loads, barriers and slot reservations overlap another's
+// arithmetic.
+constexpr int kSWaves = 8;
+constexpr int kSBlock = kSWaves * 64;
+constexpr int kMaxSGrid = 1024;               // workgroups of a streaming launch (upper bound)
 constexpr int kSRows = 8;                     // rows of point pairs per wave and tile
-constexpr int kSTilePairs = kBlock * kSRows;  // pairs per workgroup tile
+constexpr int kSTilePairs = kSBlock * kSRows;  // pairs per workgroup tile
 constexpr int kSTile = 2 * kSTilePairs;       // points per workgroup tile (16384)
 constexpr int kStreamMin = 1 << 20;           // single hulls of at least this many points take this path
 
@@ -184,7 +190,7 @@ __device__ __forceinline__ FCand wave_max_fc(const Edge& E, FCand v, bool fp64, 
     return v;
 }
 
-// Block-wide farthest point (result valid on every thread). `lds` holds kWaves entries.
+// Block-wide farthest point (result valid on every thread). `lds` holds kSWaves entries.
 __device__ __forceinline__ FCand block_max_fc(const Edge& E, FCand v, FCand* lds, bool fp64, uint32_t& n_exact)
 {
     const int w = (int)(threadIdx.x >> 6), lane = lane_id();
@@ -192,9 +198,9 @@ __device__ __forceinline__ FCand block_max_fc(const Edge& E, FCand v, FCand* lds
     __syncthreads();
     if (lane == 0) lds[w] = v;
     __syncthreads();
-    FCand r = lds[lane & (kWaves - 1)];
+    FCand r = lds[lane & (kSWaves - 1)];  // (kSWaves is a power of two)
 #pragma unroll
-    for (int m = 1; m < kWaves; m <<= 1) {
+    for (int m = 1; m < kSWaves; m <<= 1) {
         const FCand o = shfl_xor_fc(r, m);
         if (fc_beats(E, o, r, fp64, n_exact)) r = o;
     }
@@ -239,19 +245,33 @@ struct FirstPart {
 };
 
 // Per-call state of the streaming path in the workspace.
+constexpr int kSPassMaxS = 256;      // streaming passes take at most this many segments ...
+constexpr int kSPassMinV = kTinyPoints;  // ... and more than this many (fewer: k_stail)
+constexpr int kPRows = 8;            // rows of points per wave and tile in a streaming pass
+constexpr int kPTile = kSBlock * kPRows;
+
+// Farthest points of one segment's two children found by one workgroup.
+struct PassRec {
+    FCand c[2];
+};
+
 struct StreamWs {
-    SeedPart seed[kMaxChunks];
-    SplitPart split[kMaxChunks];
-    FirstPart first[kMaxChunks];
+    SeedPart seed[kMaxSGrid];
+    SplitPart split[kMaxSGrid];
+    FirstPart first[kMaxSGrid];
     SeedPart seed_res;    // A (mn*), B (mx*), non-finite flag
     SplitPart split_res;  // n_lo, n_up, C_lo, C_up
-    unsigned int done[4];   // workgroups finished: seed, split, first compaction
+    unsigned int done[4];   // workgroups finished: seed, split, first compaction, streaming pass
     unsigned int pad[60];
     unsigned int cursor[4]; // first compaction: points placed so far in each child
     unsigned int pad2[60];
-    // followed by one 64-bit count word per tile (spare)
+    int state[2];           // {survivor buffer, pass} of the next pass
+    int pad3[62];
+    unsigned int pcursor[kSPassMaxS][2];  // streaming pass: points placed so far per segment and child
+    // followed by the streaming pass's records (PassRec), one per tile that
+    // starts a workgroup's run of tiles in one segment
 };
-__device__ __forceinline__ uint64_t* stream_slots(void* ws) { return reinterpret_cast<uint64_t*>(static_cast<StreamWs*>(ws) + 1); }
+__device__ __forceinline__ PassRec* pass_recs(void* ws) { return reinterpret_cast<PassRec*>(static_cast<StreamWs*>(ws) + 1); }
 
 // the pairs of one wave's rows in tile j: pair index of row r, lane l is
 // p0 + 64 r + l
@@ -311,6 +331,30 @@ __device__ __forceinline__ void unpack_counts(uint64_t v, int (&c)[4])
 __device__ __forceinline__ int lanes_below(uint64_t M)
 {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+}
+
+// Block-wide exclusive scan of one pair per thread (kSWaves waves); *tot
+// receives the block total.
+__device__ __forceinline__ Pair sblock_excl_scan(Pair v, Pair* red, Pair* tot)
+{
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    Pair inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int oa = __shfl_up(inc.a, d), ob = __shfl_up(inc.b, d);
+        if (lane >= d) { inc.a += oa; inc.b += ob; }
+    }
+    __syncthreads();
+    if (lane == 63) red[w] = inc;
+    __syncthreads();
+    Pair off = {0, 0}, all = {0, 0};
+#pragma unroll
+    for (int u = 0; u < kSWaves; ++u) {
+        if (u < w) { off.a += red[u].a; off.b += red[u].b; }
+        all.a += red[u].a; all.b += red[u].b;
+    }
+    *tot = all;
+    return Pair{off.a + inc.a - v.a, off.b + inc.b - v.b};
 }
 
 __device__ __forceinline__ int wave_sum(int v)
@@ -428,7 +472,7 @@ __device__ __forceinline__ bool last_arrival(unsigned int* ctr, int nb)
 // Block-wide farthest point for edge o -> e (every thread gets it).
 __device__ __noinline__ FCand block_max_call(float ox, float oy, float ex, float ey, FCand v, int fp64)
 {
-    __shared__ FCand lds[kWaves];
+    __shared__ FCand lds[kSWaves];
     const Edge E = make_edge(ox, oy, ex, ey);
     uint32_t n = 0;
     return block_max_fc(E, v, lds, fp64 != 0, n);
@@ -521,7 +565,7 @@ __device__ __forceinline__ void first_pending(FirstLane* st, uint32_t pend, int 
 __device__ __forceinline__ void split_wg_partial(SplitPart* out, SplitLane s, float ax, float ay, float bx, float by,
                                               const float2* xy, int fp64)
 {
-    __shared__ int cnt[kWaves][2];
+    __shared__ int cnt[kSWaves][2];
     const int lane = lane_id(), w = wave_index();
     const int c0 = wave_sum(s.c0), c1 = wave_sum(s.c1);
     if (lane == 0) { cnt[w][0] = c0; cnt[w][1] = c1; }
@@ -530,27 +574,31 @@ __device__ __forceinline__ void split_wg_partial(SplitPart* out, SplitLane s, fl
     if (threadIdx.x == 0) {
         SplitPart sp;
         sp.cnt[0] = 0; sp.cnt[1] = 0; sp.cnt[2] = 0; sp.cnt[3] = 0;
-        for (int u = 0; u < kWaves; ++u) { sp.cnt[0] += cnt[u][0]; sp.cnt[1] += cnt[u][1]; }
+        for (int u = 0; u < kSWaves; ++u) { sp.cnt[0] += cnt[u][0]; sp.cnt[1] += cnt[u][1]; }
         sp.c[0] = f0;
         sp.c[1] = f1;
         gst(out, sp);
     }
 }
 
-// The last workgroup of the seed: A, B and the non-finite flag.
+// The last workgroup of the seed: A, B and the non-finite flag; the state
+// of the streaming passes.
 __device__ __forceinline__ void seed_finish(const HullArgs& a)
 {
-    __shared__ Lex s_lex[2][kWaves];
-    __shared__ int s_bad[kWaves];
+    __shared__ Lex s_lex[2][kSWaves];
+    __shared__ int s_bad[kSWaves];
     auto* ws = static_cast<StreamWs*>(a.sws);
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index(), nb = (int)gridDim.x;
+    if (t < 2 * kSPassMaxS) (&ws->pcursor[0][0])[t] = 0u;
+    if (t < 2) ws->state[t] = 0;
     Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
     int bad = 0;
-    if (t < nb) {
-        const SeedPart sp = gld(&ws->seed[t]);
-        mn.x = sp.mnx; mn.y = sp.mny; mn.id = sp.mni;
-        mx.x = sp.mxx; mx.y = sp.mxy; mx.id = sp.mxi;
-        bad = sp.bad;
+    for (int u = t; u < nb; u += kSBlock) {
+        const SeedPart sp = gld(&ws->seed[u]);
+        const Lex p0 = {sp.mnx, sp.mny, sp.mni}, p1 = {sp.mxx, sp.mxy, sp.mxi};
+        if (lex_beats(false, p0, mn)) mn = p0;
+        if (lex_beats(true, p1, mx)) mx = p1;
+        bad |= sp.bad;
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
@@ -564,7 +612,7 @@ __device__ __forceinline__ void seed_finish(const HullArgs& a)
     if (t == 0) {
         Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
         int qb = s_bad[0];
-        for (int u = 1; u < kWaves; ++u) {
+        for (int u = 1; u < kSWaves; ++u) {
             if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
             if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
             qb |= s_bad[u];
@@ -594,16 +642,21 @@ __device__ __forceinline__ void seed_finish(const HullArgs& a)
 // workgroups, the vertex keys of A and B.
 __device__ __forceinline__ void split_finish(const HullArgs& a, float ax, float ay, float bx, float by, int aid, int bid)
 {
-    __shared__ int cnt[kWaves][2];
+    __shared__ int cnt[kSWaves][2];
     auto* ws = static_cast<StreamWs*>(a.sws);
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index(), nb = (int)gridDim.x;
     int c0 = 0, c1 = 0;
     FCand f0 = fc_none(), f1 = fc_none();
-    if (t < nb) {
-        c0 = gld(&ws->split[t].cnt[0]);
-        c1 = gld(&ws->split[t].cnt[1]);
-        f0 = gld(&ws->split[t].c[0]);
-        f1 = gld(&ws->split[t].c[1]);
+    {
+        const Edge eab = make_edge(ax, ay, bx, by), eba = make_edge(bx, by, ax, ay);
+        uint32_t nx = 0;
+        for (int u = t; u < nb; u += kSBlock) {
+            c0 += gld(&ws->split[u].cnt[0]);
+            c1 += gld(&ws->split[u].cnt[1]);
+            const FCand g0 = gld(&ws->split[u].c[0]), g1 = gld(&ws->split[u].c[1]);
+            if (fc_beats(eab, g0, f0, a.fp64 != 0, nx)) f0 = g0;
+            if (fc_beats(eba, g1, f1, a.fp64 != 0, nx)) f1 = g1;
+        }
     }
     c0 = wave_sum(c0);
     c1 = wave_sum(c1);
@@ -612,7 +665,7 @@ __device__ __forceinline__ void split_finish(const HullArgs& a, float ax, float 
     f1 = block_max_call(bx, by, ax, ay, f1, a.fp64);
     if (t == 0) {
         int n_lo = 0, n_up = 0;
-        for (int u = 0; u < kWaves; ++u) { n_lo += cnt[u][0]; n_up += cnt[u][1]; }
+        for (int u = 0; u < kSWaves; ++u) { n_lo += cnt[u][0]; n_up += cnt[u][1]; }
         SplitPart r;
         r.cnt[0] = n_lo; r.cnt[1] = n_up; r.cnt[2] = 0; r.cnt[3] = 0;
         r.c[0] = f0;
@@ -659,8 +712,13 @@ __device__ __forceinline__ void first_finish(const HullArgs& a, FirstGeo g, int 
     FCand C[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+        const Edge E = make_edge(ex[k], ey[k], ex[k + 1], ey[k + 1]);
+        uint32_t nx = 0;
         FCand f = fc_none();
-        if (t < nb) f = gld(&ws->first[t].c[k]);
+        for (int u = t; u < nb; u += kSBlock) {
+            const FCand g2 = gld(&ws->first[u].c[k]);
+            if (fc_beats(E, g2, f, a.fp64 != 0, nx)) f = g2;
+        }
         C[k] = block_max_call(ex[k], ey[k], ex[k + 1], ey[k + 1], f, a.fp64);
     }
     if (t == 0) {
@@ -693,10 +751,10 @@ __device__ __forceinline__ void first_finish(const HullArgs& a, FirstGeo g, int 
 // Lexicographic minimum and maximum of the input (section 4.3: the leftmost
 // and rightmost points; coincident points: the lowest index) and the
 // non-finite check.
-__global__ __launch_bounds__(kBlock) void k_sseed(HullArgs a)
+__global__ __launch_bounds__(kSBlock) void k_sseed(HullArgs a)
 {
-    __shared__ Lex s_lex[2][kWaves];
-    __shared__ int s_bad[kWaves];
+    __shared__ Lex s_lex[2][kSWaves];
+    __shared__ int s_bad[kSWaves];
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int n = a.N;
@@ -739,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_sseed(HullArgs a)
     if (t == 0) {
         Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
         int qb = s_bad[0];
-        for (int u = 1; u < kWaves; ++u) {
+        for (int u = 1; u < kSWaves; ++u) {
             if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
             if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
             qb |= s_bad[u];
@@ -759,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_sseed(HullArgs a)
 // Side of every point w.r.t. the line A->B (section 4.3) and the farthest
 // point of each side (section 4.4.1). Points on the line belong to neither
 // side.
-__global__ __launch_bounds__(kBlock) void k_ssplit(HullArgs a)
+__global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
 {
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int lane = lane_id(), w = wave_index();
@@ -827,10 +885,10 @@ __global__ __launch_bounds__(kBlock) void k_ssplit(HullArgs a)
 // therefore that of the reservations, which no later step depends on (every
 // decision is geometric, with index tie-breaks). The last workgroup to finish
 // writes the first pass's segment table.
-__global__ __launch_bounds__(kBlock) void k_sfirst(HullArgs a)
+__global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
 {
-    __shared__ int s_wcnt[kWaves][4];  // per-wave child counts of the current tile
-    __shared__ int s_wbase[kWaves][4]; // ... as offsets inside the tile's reservation
+    __shared__ int s_wcnt[kSWaves][4];  // per-wave child counts of the current tile
+    __shared__ int s_wbase[kSWaves][4]; // ... as offsets inside the tile's reservation
     __shared__ int s_base[4];          // the tile's first rank in each child
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
@@ -914,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_sfirst(HullArgs a)
         if (t < 4) {
             // per-wave offsets inside the tile, and the tile's reservation
             int run = 0;
-            for (int u = 0; u < kWaves; ++u) {
+            for (int u = 0; u < kSWaves; ++u) {
                 s_wbase[u][t] = run;
                 run += s_wcnt[u][t];
             }
@@ -968,6 +1026,348 @@ __global__ __launch_bounds__(kBlock) void k_sfirst(HullArgs a)
         const int c2 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[2]));
         const int c3 = (int)ld_flag(reinterpret_cast<const int*>(&ws->cursor[3]));
         first_finish(a, g, n_lo, n_up, pr.c[0].id, pr.c[1].id, c0, c1, c2, c3);
+    }
+}
+
+// ========================================================== streaming pass
+// One pass of section 4.4 over a segment table of at most kSPassMaxS
+// segments holding at least kSPassMinV points (the first passes of large
+// hulls: few segments, millions of points). Tiles of kPTile points never
+// straddle segments, so a tile's edges A->C and C->B are uniform; a tile
+// reserves its slots in each child with one atomic add (child (A, C) fills
+// the parent's slots from the front, (C, B) from the back); a workgroup keeps
+// its lanes' farthest candidates while its tiles stay in one segment and
+// then reduces them once. The last workgroup to finish writes the next
+// segment table. An ordinary launch; when the table does not qualify it
+// does nothing, and the passes kernel continues from the same state.
+struct SSeg {
+    float ax, ay, bx, by, cx, cy;  // A, B and the farthest point C
+    int off, len, cid, t0;         // slots, C's index, first tile
+};
+
+__device__ __forceinline__ int pass_fast(const SSeg& g, float x, float y, bool valid, bool fp64, float& a, float& w)
+{
+    const Orient32 o1 = orient32p(g.ax, g.ay, g.cx, g.cy, x, y);  // A -> C
+    const Orient32 o2 = orient32p(g.cx, g.cy, g.bx, g.by, x, y);  // C -> B
+    const int s1 = fsign(o1, fp64), s2 = fsign(o2, fp64);
+    const bool in1 = s1 < 0, in2 = !in1 & (s2 < 0);
+    a = -(in1 ? o1.d : o2.d);
+    w = 2.0f * (in1 ? o1.es : o2.es);
+    const bool und = (s1 == 0) | ((s1 > 0) & (s2 == 0));
+    return !valid ? 7 : (und ? 15 : (in1 ? 0 : (in2 ? 1 : 7)));
+}
+
+__device__ __forceinline__ int pass_classify(const SSeg& g, float x, float y, bool fp64, float& a, float& w,
+                                             uint32_t& n_exact)
+{
+    const Orient32 o1 = orient32p(g.ax, g.ay, g.cx, g.cy, x, y);
+    const Orient32 o2 = orient32p(g.cx, g.cy, g.bx, g.by, x, y);
+    int s1 = fsign(o1, fp64), s2 = fsign(o2, fp64);
+    settle_inl(s1, s1 == 0, g.ax, g.ay, g.cx, g.cy, x, y, n_exact);
+    settle_inl(s2, (s1 >= 0) & (s2 == 0), g.cx, g.cy, g.bx, g.by, x, y, n_exact);
+    const bool in1 = s1 < 0, in2 = !in1 & (s2 < 0);
+    a = -(in1 ? o1.d : o2.d);
+    w = 2.0f * (in1 ? o1.es : o2.es);
+    return in1 ? 0 : (in2 ? 1 : 7);
+}
+
+// Workgroup b of nb takes tiles [tile_lo(b), tile_lo(b + 1)) of T; the
+// owner of tile j is the last b with tile_lo(b) <= j.
+__device__ __forceinline__ int tile_lo(int b, int nb, int T) { return (int)((long long)b * T / nb); }
+__device__ __forceinline__ int tile_owner(int j, int nb, int T) { return (int)(((long long)(j + 1) * nb - 1) / T); }
+
+__global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
+{
+    __shared__ SSeg s_seg[kSPassMaxS + 1];
+    __shared__ int s_wcnt[kSWaves][2];
+    __shared__ int s_wbase[kSWaves][2];
+    __shared__ int s_base[2];
+    __shared__ Pair s_red[kSWaves];
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
+    const int fp64 = a.fp64;
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    PassRec* recs = pass_recs(a.sws);
+    if (ld_flag(a.err)) return;
+    const int cur = ld_flag(&ws->state[0]) & 1, pass = ld_flag(&ws->state[1]), nxt = cur ^ 1;
+    const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
+    if (S <= 0 || S > kSPassMaxS || V <= kSPassMinV || pass >= kMaxInfoPasses) return;  // uniform
+    // the segment table and each segment's first tile
+    {
+        SSeg g = {};
+        int nt = 0;
+        if (t < S) {
+            const Seg q = gld(a.segs[cur] + t);
+            g.ax = q.ax; g.ay = q.ay; g.bx = q.bx; g.by = q.by; g.cx = q.cx; g.cy = q.cy;
+            g.off = q.off; g.len = q.len;
+            g.cid = gld(a.seg_cid[cur] + t);
+            nt = (q.len + kPTile - 1) / kPTile;
+        }
+        Pair tot;
+        const Pair ex = sblock_excl_scan(Pair{nt, 0}, s_red, &tot);
+        if (t < S) {
+            g.t0 = ex.a;
+            s_seg[t] = g;
+        }
+        if (t == 0) s_seg[S].t0 = tot.a;
+        __syncthreads();
+    }
+    const int ntiles = s_seg[S].t0;
+    const int jlo = tile_lo(b, nb, ntiles), jhi = tile_lo(b + 1, nb, ntiles);
+    float* Xo = a.X[nxt];
+    float* Yo = a.Y[nxt];
+    int* Io = a.I[nxt];
+    const float* Xi = a.X[cur];
+    const float* Yi = a.Y[cur];
+    const int* Ii = a.I[cur];
+    LCand q0 = lc_none(), q1 = lc_none();
+    uint32_t n_orient = 0u, n_oexact = 0u, n_cexact = 0u;
+    int s = 0;  // segment of tile j
+    if (jlo < jhi) {
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_seg[mid].t0 <= jlo) lo = mid;
+            else hi = mid - 1;
+        }
+        s = lo;
+    }
+    int run_j0 = jlo;  // first tile of this workgroup's run in segment s
+    for (int j = jlo; j < jhi; ++j) {
+        while (s_seg[s + 1].t0 <= j) {
+            ++s;
+            run_j0 = j;
+        }
+        const SSeg g = s_seg[s];
+        const int q0pos = (j - g.t0) * kPTile + w * (kPRows * 64);  // this wave's first position
+        const bool full = q0pos + kPRows * 64 <= g.len;             // uniform per wave
+        uint32_t code = 0u;  // 4 bits per row
+        {
+            float x[kPRows], y[kPRows];
+            int id[kPRows];
+#pragma unroll
+            for (int r = 0; r < kPRows; ++r) {
+                const int pos = q0pos + 64 * r + lane;
+                const bool m = full | (pos < g.len);
+                const int p = g.off + (m ? pos : 0);
+                x[r] = gld(Xi + p); y[r] = gld(Yi + p); id[r] = gld(Ii + p);
+            }
+            uint32_t pend = 0u;
+#pragma unroll
+            for (int r = 0; r < kPRows; ++r) {
+                const bool m = full | (q0pos + 64 * r + lane < g.len);
+                float ar, wr;
+                int c = pass_fast(g, x[r], y[r], m, fp64 != 0, ar, wr);
+                const float lo2 = ar - wr, hi2 = ar + wr;
+                bool und = c == 15;
+                und |= lc_offer_fast(q0, c == 0, lo2, hi2, id[r], fp64 != 0);
+                und |= lc_offer_fast(q1, c == 1, lo2, hi2, id[r], fp64 != 0);
+                c = und ? 15 : c;
+                pend |= (uint32_t)und << r;
+                n_orient += m ? 2u : 0u;
+                code |= (uint32_t)c << (4 * r);
+            }
+            if (__ballot(pend != 0u)) {
+                const Edge e0 = make_edge(g.ax, g.ay, g.cx, g.cy), e1 = make_edge(g.cx, g.cy, g.bx, g.by);
+#pragma unroll 1
+                for (int r = 0; r < kPRows; ++r) {
+                    const bool mine = (pend >> r) & 1u;
+                    if (!__ballot(mine)) continue;
+                    if (mine) {
+                        const int p = g.off + q0pos + 64 * r + lane;
+                        const float px = gld(Xi + p), py = gld(Yi + p);
+                        const int pid = gld(Ii + p);
+                        float ar, wr;
+                        const int c = pass_classify(g, px, py, fp64 != 0, ar, wr, n_oexact);
+                        const float lo2 = ar - wr, hi2 = ar + wr;
+                        lc_offer(q0, c == 0, lo2, hi2, pid, px, py, e0, a.xy, fp64 != 0, n_cexact);
+                        lc_offer(q1, c == 1, lo2, hi2, pid, px, py, e1, a.xy, fp64 != 0, n_cexact);
+                        code = (code & ~(15u << (4 * r))) | ((uint32_t)c << (4 * r));
+                    }
+                }
+            }
+        }
+        int wc0 = 0, wc1 = 0;
+#pragma unroll
+        for (int r = 0; r < kPRows; ++r) {
+            const int c = (int)(code >> (4 * r)) & 15;
+            wc0 += __popcll(__ballot(c == 0));
+            wc1 += __popcll(__ballot(c == 1));
+        }
+        if (lane == 0) { s_wcnt[w][0] = wc0; s_wcnt[w][1] = wc1; }
+        __syncthreads();
+        if (t < 2) {
+            int run = 0;
+            for (int u = 0; u < kSWaves; ++u) {
+                s_wbase[u][t] = run;
+                run += s_wcnt[u][t];
+            }
+            s_base[t] = run > 0 ? (int)atomicAdd(&ws->pcursor[s][t], (unsigned int)run) : 0;
+        }
+        __syncthreads();
+        {
+            // scatter (the tile is read again, from the L2 cache)
+            int run0 = s_base[0] + s_wbase[w][0], run1 = s_base[1] + s_wbase[w][1];
+#pragma unroll
+            for (int r = 0; r < kPRows; ++r) {
+                const int pos = q0pos + 64 * r + lane;
+                const int c = (int)(code >> (4 * r)) & 15;
+                const uint64_t M0 = __ballot(c == 0), M1 = __ballot(c == 1);
+                const int dst = c == 0 ? g.off + run0 + lanes_below(M0) : g.off + g.len - 1 - (run1 + lanes_below(M1));
+                if (c < 2) {
+                    const int p = g.off + pos;
+                    gst(Xo + dst, gld(Xi + p));
+                    gst(Yo + dst, gld(Yi + p));
+                    gst(Io + dst, gld(Ii + p));
+                }
+                run0 += __popcll(M0);
+                run1 += __popcll(M1);
+            }
+        }
+        // the run of tiles in segment s ends here: reduce the candidates once
+        if (j + 1 == jhi || s_seg[s + 1].t0 <= j + 1) {
+            PassRec rc;
+            rc.c[0] = block_max_call(g.ax, g.ay, g.cx, g.cy, lc_full(q0, a.xy), fp64);
+            rc.c[1] = block_max_call(g.cx, g.cy, g.bx, g.by, lc_full(q1, a.xy), fp64);
+            if (t == 0) gst(recs + run_j0, rc);
+            q0 = lc_none();
+            q1 = lc_none();
+        }
+        __syncthreads();
+    }
+    Counters ctr = {n_orient, n_oexact, n_cexact};
+    flush_counters(a.stats, ctr);
+    if (!last_arrival(&ws->done[3], nb)) return;
+    // ---- the last workgroup: each segment's children (farthest points over
+    // the records of the workgroups that took its tiles, counts from the
+    // cursors), the vertex key of its farthest point, and the next table
+    __shared__ FCand s_c[kSPassMaxS][2];
+    __shared__ int s_big[kSPassMaxS];
+    __shared__ int s_nbig;
+    if (t == 0) s_nbig = 0;
+    __syncthreads();
+    if (t < S) {
+        const SSeg g = s_seg[t];
+        const int t1 = s_seg[t + 1].t0;
+        const int bl = tile_owner(g.t0, nb, ntiles), bh = tile_owner(t1 - 1, nb, ntiles);
+        if (bh - bl < 8) {
+            const Edge e0 = make_edge(g.ax, g.ay, g.cx, g.cy), e1 = make_edge(g.cx, g.cy, g.bx, g.by);
+            FCand v0 = fc_none(), v1 = fc_none();
+            uint32_t nx = 0;
+            for (int u = bl; u <= bh; ++u) {
+                const PassRec r = gld(recs + max(g.t0, tile_lo(u, nb, ntiles)));
+                if (fc_beats(e0, r.c[0], v0, fp64 != 0, nx)) v0 = r.c[0];
+                if (fc_beats(e1, r.c[1], v1, fp64 != 0, nx)) v1 = r.c[1];
+            }
+            s_c[t][0] = v0;
+            s_c[t][1] = v1;
+        } else {
+            s_big[atomicAdd(&s_nbig, 1)] = t;
+        }
+    }
+    __syncthreads();
+    for (int i = w; i < s_nbig; i += kSWaves) {
+        const int s2 = s_big[i];
+        const SSeg g = s_seg[s2];
+        const int t1 = s_seg[s2 + 1].t0;
+        const int bl = tile_owner(g.t0, nb, ntiles), bh = tile_owner(t1 - 1, nb, ntiles);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const Edge E = k == 0 ? make_edge(g.ax, g.ay, g.cx, g.cy) : make_edge(g.cx, g.cy, g.bx, g.by);
+            FCand v = fc_none();
+            uint32_t nx = 0;
+            for (int u = bl + lane; u <= bh; u += 64) {
+                const FCand o = gld(&recs[max(g.t0, tile_lo(u, nb, ntiles))].c[k]);
+                if (fc_beats(E, o, v, fp64 != 0, nx)) v = o;
+            }
+            v = wave_max_fc(E, v, fp64 != 0, nx);
+            if (lane == 0) s_c[s2][k] = v;
+        }
+    }
+    __syncthreads();
+    int n0 = 0, n1 = 0;
+    SSeg g = {};
+    if (t < S) {
+        g = s_seg[t];
+        n0 = (int)ld_flag(reinterpret_cast<const int*>(&ws->pcursor[t][0]));
+        n1 = (int)ld_flag(reinterpret_cast<const int*>(&ws->pcursor[t][1]));
+    }
+    Pair tot;
+    const Pair ex = sblock_excl_scan(Pair{(n0 > 0) + (n1 > 0), n0 + n1}, s_red, &tot);
+    int2* vl = (a.vcap > 0) ? a.vlist : nullptr;
+    if (t < S) {
+        // C's key is the first slot after the (A, C) points (section 4.4.2)
+        record_vertex(a.bitmap, a.vidx, vl, a.info, g.off + n0, g.cid);
+        int k = ex.a, vs = ex.b;
+        if (n0 > 0) {
+            Seg r;
+            r.ax = g.ax; r.ay = g.ay; r.bx = g.cx; r.by = g.cy;
+            r.cx = s_c[t][0].x; r.cy = s_c[t][0].y;
+            r.off = g.off; r.len = n0;
+            gst(a.segs[nxt] + k, r);
+            a.seg_cid[nxt][k] = s_c[t][0].id;
+            a.vstart[nxt][k] = vs;
+            ++k;
+            vs += n0;
+        }
+        if (n1 > 0) {
+            Seg r;
+            r.ax = g.cx; r.ay = g.cy; r.bx = g.bx; r.by = g.by;
+            r.cx = s_c[t][1].x; r.cy = s_c[t][1].y;
+            r.off = g.off + g.len - n1; r.len = n1;
+            gst(a.segs[nxt] + k, r);
+            a.seg_cid[nxt][k] = s_c[t][1].id;
+            a.vstart[nxt][k] = vs;
+        }
+    }
+    __syncthreads();  // every thread has read the cursors
+    if (t < 2 * kSPassMaxS) (&ws->pcursor[0][0])[t] = 0u;
+    if (t == 0) {
+        a.vstart[nxt][tot.a] = tot.b;
+        a.sv[2 * nxt] = tot.a;
+        a.sv[2 * nxt + 1] = tot.b;
+        if (pass == 0) a.info->first_v = V;
+        a.info->pass_s[pass] = S;
+        a.info->pass_v[pass] = V;
+        a.info->passes = pass + 1;
+        a.info->spass_n = pass + 1;
+        ws->state[0] = nxt;
+        ws->state[1] = pass + 1;
+        ws->done[3] = 0u;
+        stamp_here(a, 100 + pass);
+    }
+}
+
+// The streaming path's last kernel (one workgroup, an ordinary launch): once
+// at most kTinyPoints points are left, the remaining passes in LDS (the
+// passes kernel's own tail) and the ordered emission of the vertex list.
+// Leaves info->stream_done = 1 when the hull is complete; otherwise (more
+// points left, or a vertex list too long for one workgroup) the passes
+// kernel continues from the state left in the workspace.
+__global__ __launch_bounds__(kBlock) void k_stail(HullArgs a)
+{
+    __shared__ uint4 lds[(sizeof(TinyLds) > sizeof(int2) * kSmallHull ? sizeof(TinyLds) : sizeof(int2) * kSmallHull) /
+                             16 + 1];
+    __shared__ Pair red[kWaves];
+    auto* ws = static_cast<StreamWs*>(a.sws);
+    Counters ctr = {0u, 0u, 0u};
+    if (ld_flag(a.err)) return;
+    const int cur = ld_flag(&ws->state[0]) & 1, pass = ld_flag(&ws->state[1]);
+    const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
+    if (S > 0 && (V > kTinyPoints || pass >= kMaxInfoPasses)) return;  // left to the passes kernel
+    if (S > 0) {
+        tiny_passes(a, cur, pass, *reinterpret_cast<TinyLds*>(lds), red, ctr);
+        flush_counters(a.stats, ctr);
+    } else if (threadIdx.x == 0) {
+        note_pass(a, pass, 0, 0);
+    }
+    __syncthreads();
+    const int h = ld_flag(&a.info->vcount);
+    if (!(h <= kSmallHull && h <= a.vcap)) return;  // the grid emission in the passes kernel
+    emit_small(a, h, reinterpret_cast<int2*>(lds));
+    if (threadIdx.x == 0) {
+        a.info->stream_done = 1;
+        stamp(a, 4);
     }
 }
 

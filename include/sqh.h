@@ -55,8 +55,9 @@ extern "C" {
 #define SQH_ENOTFOUND  -6  /* engine: nothing finished yet */
 
 /* Predicate precision modes (sqh_set_precision). */
-#define SQH_FP32_FILTER 0  /* float32 filter, exact float64 expansion on failure */
-#define SQH_FP64_ONLY   1  /* every predicate evaluated exactly in float64 */
+#define SQH_FP32_FILTER     0  /* float32 filters, exact float64 expansion on failure */
+#define SQH_FP64_ONLY       1  /* every predicate evaluated exactly in float64 */
+#define SQH_FP32_SEMISTATIC 2  /* as SQH_FP32_FILTER without the static line filter */
 
 /* Pre-filter of single hulls (sqh_set_prefilter). */
 #define SQH_PREFILTER_NONE    0  /* the plain method */
@@ -98,6 +99,9 @@ typedef struct sqh_stats {
     double  ms_sort;          /* sorted-chain variant: the sort of the first segments */
     int64_t sorted_points;    /* sorted-chain variant: points sorted; -1: no sort ran */
     int64_t sort_violations;  /* sorted-chain variant: neighbours found out of order after the sort (0) */
+    int64_t stream_path;      /* 0: general path; 1: the streaming kernels finished the hull;
+                                 2: ... and the passes kernel took over (more than 256 segments) */
+    int64_t line_filter;      /* 1: the streaming path used the static line filter */
 } sqh_stats;
 
 /*
@@ -111,9 +115,28 @@ int sqh_create(sqh_ctx **ctx, int device);
 /* Destroy a context created by sqh_create. NULL is ignored. */
 void sqh_destroy(sqh_ctx *ctx);
 
-/* Select SQH_FP32_FILTER (default) or SQH_FP64_ONLY. Outputs are identical;
- * only speed and the exact-path counters differ. */
+/*
+ * Select the predicate precision. SQH_FP32_FILTER (default): each
+ * orientation test first takes a float32 filter with a certified error
+ * bound (the semi-static bound of the points' offsets, or, on the streaming
+ * path when every |coordinate| is at most 2^60 and the input is not far
+ * from the origin compared with its extent, a static bound fixed per edge
+ * from the input's extent: two FMAs a test); undecided tests take the
+ * exact float64 expansion. SQH_FP32_SEMISTATIC: the semi-static filter
+ * only. SQH_FP64_ONLY: every test exact. Outputs are identical; only speed
+ * and the exact-path counters differ. Returns SQH_OK or SQH_EINVAL.
+ */
 int sqh_set_precision(sqh_ctx *ctx, int mode);
+
+/*
+ * Streaming path on (on != 0, the default) or off. On, a call on one set of
+ * at least 2^20 points (no pre-filter, partition variant, 16-byte aligned
+ * input) runs its first phases and passes over few large segments as
+ * ordinary launches that never wait for one another, and the cooperative
+ * passes kernel only for what they leave. The output is identical either
+ * way. Returns SQH_OK or SQH_EINVAL.
+ */
+int sqh_set_streaming(sqh_ctx *ctx, int on);
 
 /*
  * Pre-filter for calls on one set (sqh_hull, or a batch of one set; the

@@ -28,7 +28,7 @@ constexpr size_t kAlign = 256;
 // nothing once the segment table no longer qualifies); a context enqueues one
 // more than the previous call of the same size class needed.
 constexpr int kStreamPassLaunches = 8;
-constexpr int kMaxLaunches = 12;
+constexpr int kMaxLaunches = 16;
 constexpr int kMaxGrid = kMaxChunks;  // workgroups of the persistent kernel (upper bound)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -142,6 +142,7 @@ struct sqh_ctx {
     int device = 0;
     int cus = 0;
     int fp64 = 0;
+    int line = 1;      // the streaming path may use the static line filter
     int max_grid = 0;  // co-resident workgroups of k_hull
     int trace = 0;     // SQH_TRACE=1: per-workgroup timestamps in the info block
     hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
@@ -270,6 +271,7 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
                    : 0;
     a.start = a.stream ? static_cast<StreamWs*>(a.sws)->state : nullptr;
     a.spasses = kStreamPassLaunches;
+    a.line_ok = ctx->line;
     const int64_t work = std::max<int64_t>(std::max<int64_t>(a.W, 4 * nsets), nsets + 1);
     reset_grid = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256));
     return SQH_OK;
@@ -300,7 +302,8 @@ inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fall
     if (a.stream) {
         add(reinterpret_cast<const void*>(k_sseed), 0);
         add(reinterpret_cast<const void*>(k_ssplit), 0);
-        add(reinterpret_cast<const void*>(k_sfirst), 0);
+        add(reinterpret_cast<const void*>(k_sfirst<true>), 0);
+        add(reinterpret_cast<const void*>(k_sfirst<false>), 0);
         for (int i = 0; i < a.spasses; ++i) add(reinterpret_cast<const void*>(k_spass), 0);
         add(reinterpret_cast<const void*>(k_stail), 0);
         if (fallback) add(reinterpret_cast<const void*>(k_hull<kHullPasses>), 1);
@@ -385,6 +388,8 @@ int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t
     S.prefilter_points = hi.prefilter_n;
     S.sorted_points = hi.sort_n;
     S.sort_violations = hi.sort_bad;
+    S.stream_path = a.stream ? (hi.stream_done ? 1 : 2) : 0;
+    S.line_filter = a.stream ? hi.stream_line : 0;
     if (timed) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) S.ms_total = ms;
@@ -705,8 +710,16 @@ int sqh_set_variant(sqh_ctx* c, int variant)
 
 int sqh_set_precision(sqh_ctx* c, int mode)
 {
-    if (!c || (mode != SQH_FP32_FILTER && mode != SQH_FP64_ONLY)) return SQH_EINVAL;
+    if (!c || (mode != SQH_FP32_FILTER && mode != SQH_FP64_ONLY && mode != SQH_FP32_SEMISTATIC)) return SQH_EINVAL;
     c->fp64 = mode == SQH_FP64_ONLY;
+    c->line = mode == SQH_FP32_FILTER;
+    return SQH_OK;
+}
+
+int sqh_set_streaming(sqh_ctx* c, int on)
+{
+    if (!c) return SQH_EINVAL;
+    c->stream = on != 0;
     return SQH_OK;
 }
 

@@ -759,6 +759,7 @@ struct HullInfo {
     int sort_bad;     // sorted-chain variant: neighbours out of order after the sort
     int stream_done;  // streaming path: the hull is complete before the passes kernel
     int spass_n;      // streaming path: passes run by k_spass
+    int stream_line;  // streaming path: the static line filter was used
     int pass_s[kMaxInfoPasses];
     int pass_v[kMaxInfoPasses];
     int nstamps;
@@ -827,8 +828,9 @@ struct HullArgs {
     void* sws;
     unsigned int* sdone;     // the streaming kernels' completion counters (cleared by k_reset)
     const int* start;        // null, or {survivor buffer, pass} where k_hull<kHullPasses> starts
-    int stream;
-    int spasses;             // streaming path: k_spass launches in this call              // 1: the streaming kernels run the first phases, k_hull<kHullPasses> the rest
+    int stream;              // 1: the streaming kernels run the first phases, k_hull<kHullPasses> the rest
+    int spasses;             // streaming path: k_spass launches in this call
+    int line_ok;             // streaming path: the static line filter may be used
 };
 
 
@@ -2098,6 +2100,7 @@ __global__ void k_reset(HullArgs a)
         a.info->sort_bad = 0;
         a.info->stream_done = 0;
         a.info->spass_n = 0;
+        a.info->stream_line = 0;
     }
     if (gtid < kBarSub) a.bar->sub[gtid][0] = 0;
     if (a.stream && gtid < 4) a.sdone[gtid] = 0u;

@@ -232,8 +232,43 @@ struct SeedPart {
     float mxx, mxy;
     int mxi;
     int bad;
-    int pad;
+    int line;        // result only: the line filter applies (see LineF)
+    float ylo, yhi;  // y range (the x range is [mnx, mxx])
+    float Mx, My;    // result only: bounds on |x| and |y|
 };
+
+// Static line filter for the edge o -> e (the pre-filter's line test, with
+// the error bound derived there): t(p) = fma(-dy, px, fma(dx, py, c)) with
+// dx, dy = fl(e - o) and c = fl(fl(dy ox) - fl(dx oy)) differs from
+// orient(o, e, p) by less than m = 2^-19 (|dx| My + |dy| Mx) + 2^-140 for
+// every point of the input (Mx, My bound |x|, |y| over it, at most 2^60),
+// so t < -m certifies orient < 0, t > m certifies orient > 0, and
+// [-t - m, -t + m] encloses the area -orient. One evaluation is two FMAs;
+// the constants come from the input's extent, once per edge.
+struct LineF {
+    float nx, ny, c, m;
+};
+__device__ __forceinline__ LineF make_line(float ox, float oy, float ex, float ey, float Mx, float My)
+{
+    const float dx = ex - ox, dy = ey - oy;
+    LineF L;
+    L.nx = -dy;
+    L.ny = dx;
+    L.c = dy * ox - dx * oy;
+    L.m = (fabsf(dx) * My + fabsf(dy) * Mx) * kLineRel + kFilterTau;
+    return L;
+}
+// an edge no point is strictly right of (a side without points)
+__device__ __forceinline__ LineF line_never()
+{
+    LineF L;
+    L.nx = 0.0f; L.ny = 0.0f; L.c = INFINITY; L.m = 0.0f;
+    return L;
+}
+__device__ __forceinline__ float line_eval(const LineF& L, float px, float py)
+{
+    return fmaf(L.nx, px, fmaf(L.ny, py, L.c));
+}
 
 struct SplitPart {
     int cnt[4];
@@ -396,6 +431,65 @@ __device__ __forceinline__ int first_fast(const FirstGeo& g, float x, float y, b
     return !valid ? 7 : (und ? 15 : (in1 ? b : (in2 ? b + 1 : 7)));
 }
 
+// The same with the line filter of the four edges A->C_lo, C_lo->B, B->C_up,
+// C_up->A: a point belongs to the child whose edge it is strictly right of.
+// This is the rule above: a point right of A->C_lo or C_lo->B is right of
+// A->B (A is the lexicographic minimum, so seen from A every point lies in
+// a half-plane where "clockwise of" orders directions), likewise for the
+// upper edges seen from B, and no point is right of both edges of one side
+// (C is the farthest point). So one certified negative edge decides the
+// child, four certified positive edges discard the point, and anything else
+// is settled exactly.
+__device__ __forceinline__ int first_line(const LineF (&L)[4], float x, float y, bool valid, float& a, float& w)
+{
+    const float t0 = line_eval(L[0], x, y), t1 = line_eval(L[1], x, y);
+    const float t2 = line_eval(L[2], x, y), t3 = line_eval(L[3], x, y);
+    const bool n0 = t0 < -L[0].m, n1 = t1 < -L[1].m, n2 = t2 < -L[2].m, n3 = t3 < -L[3].m;
+    const bool p0 = t0 > L[0].m, p1 = t1 > L[1].m, p2 = t2 > L[2].m, p3 = t3 > L[3].m;
+    const int code = n0 ? 0 : (n1 ? 1 : (n2 ? 2 : (n3 ? 3 : 7)));
+    const float ts = n0 ? t0 : (n1 ? t1 : (n2 ? t2 : t3));
+    w = n0 ? L[0].m : (n1 ? L[1].m : (n2 ? L[2].m : L[3].m));
+    a = -ts;
+    const bool und = !(n0 | n1 | n2 | n3) & !(p0 & p1 & p2 & p3);
+    return !valid ? 7 : (und ? 15 : code);
+}
+
+struct FirstLane {
+    LCand q[4];
+    uint32_t code_lo, code_hi;
+    uint32_t n_orient_exact, n_cmp_exact;
+};
+
+// Filter-only pass over one wave's rows of a tile: codes (4 bits per point,
+// 15 = settle exactly) and the lanes' candidates; returns the pending mask.
+template <bool LINE>
+__device__ __forceinline__ uint32_t first_fast_rows(FirstLane& s, const float4 (&v)[kSRows], int p0, int n,
+                                                    const FirstGeo& g, const LineF (&L)[4], bool fp64)
+{
+    uint32_t pend = 0u;
+#pragma unroll
+    for (int rr = 0; rr < kSRows; ++rr) {
+        const int id0 = 2 * (p0 + 64 * rr);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
+            const bool m = id0 + h < n;
+            float ar, wr;
+            int code = LINE ? first_line(L, x, y, m, ar, wr) : first_fast(g, x, y, m, fp64, ar, wr);
+            const float lo = ar - wr, hi = ar + wr;
+            bool und = code == 15;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) und |= lc_offer_fast(s.q[k], code == k, lo, hi, id0 + h, fp64);
+            code = und ? 15 : code;
+            pend |= (uint32_t)und << (2 * rr + h);
+            const int sh = 4 * (2 * (rr & 3) + h);
+            if (rr < 4) s.code_lo |= (uint32_t)code << sh;
+            else s.code_hi |= (uint32_t)code << sh;
+        }
+    }
+    return pend;
+}
+
 __device__ __forceinline__ int first_classify(const FirstGeo& g, float x, float y, bool valid, bool fp64, float& a,
                                               float& w, Counters& ctr)
 {
@@ -449,6 +543,20 @@ __device__ __forceinline__ void stamp_here(const HullArgs& a, int tag)
 
 __device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
+// Values every lane holds alike, moved to scalar registers (results loaded
+// through vector loads otherwise stay in vector registers).
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ SeedPart uni(const SeedPart& p)
+{
+    SeedPart r;
+    r.mnx = uni(p.mnx); r.mny = uni(p.mny); r.mni = uni(p.mni);
+    r.mxx = uni(p.mxx); r.mxy = uni(p.mxy); r.mxi = uni(p.mxi);
+    r.bad = uni(p.bad); r.line = uni(p.line);
+    r.ylo = uni(p.ylo); r.yhi = uni(p.yhi); r.Mx = uni(p.Mx); r.My = uni(p.My);
+    return r;
+}
+
 // True on the workgroup that arrives last at counter *ctr (nb arrivals), after
 // it has acquired every earlier arrival's writes.
 __device__ __forceinline__ bool last_arrival(unsigned int* ctr, int nb)
@@ -501,8 +609,7 @@ __device__ __forceinline__ void split_pending(SplitLane* st, uint32_t pend, int 
             const int id = 2 * (p0 + 64 * (i >> 1)) + (i & 1);
             const float2 P = gld(xy + id);
             const Orient32 o = orient32p(ax, ay, bx, by, P.x, P.y);
-            const int f = fast_sign(o, f64);
-            int sg = f;
+            int sg = fast_sign(o, f64);
             if (sg == 0) {
                 sg = orient_exact_inl(ax, ay, bx, by, P.x, P.y);
                 ++s.n_orient_exact;
@@ -510,11 +617,9 @@ __device__ __forceinline__ void split_pending(SplitLane* st, uint32_t pend, int 
             const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
             const float lo = ar - wr, hi = ar + wr;
             const bool lower = sg < 0, upper = sg > 0;
-            // the fast pass counted the point iff its side was certified
-            if (f == 0) {
-                s.c0 += lower ? 1 : 0;
-                s.c1 += upper ? 1 : 0;
-            }
+            // the fast pass neither counted nor offered a pending point
+            s.c0 += lower ? 1 : 0;
+            s.c1 += upper ? 1 : 0;
             lc_offer(s.q0, lower, lo, hi, id, P.x, P.y, eab, xy, f64, s.n_cmp_exact);
             lc_offer(s.q1, upper, lo, hi, id, P.x, P.y, eba, xy, f64, s.n_cmp_exact);
         }
@@ -522,11 +627,7 @@ __device__ __forceinline__ void split_pending(SplitLane* st, uint32_t pend, int 
     *st = s;
 }
 
-struct FirstLane {
-    LCand q[4];
-    uint32_t code_lo, code_hi;
-    uint32_t n_orient_exact, n_cmp_exact;
-};
+
 
 __device__ __forceinline__ void first_pending(FirstLane* st, uint32_t pend, int p0, FirstGeo g, const float2* xy,
                                            int fp64)
@@ -593,12 +694,15 @@ __device__ __forceinline__ void seed_finish(const HullArgs& a)
     if (t < 2) ws->state[t] = 0;
     Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
     int bad = 0;
+    float ylo = INFINITY, yhi = -INFINITY;
     for (int u = t; u < nb; u += kSBlock) {
         const SeedPart sp = gld(&ws->seed[u]);
         const Lex p0 = {sp.mnx, sp.mny, sp.mni}, p1 = {sp.mxx, sp.mxy, sp.mxi};
         if (lex_beats(false, p0, mn)) mn = p0;
         if (lex_beats(true, p1, mx)) mx = p1;
         bad |= sp.bad;
+        ylo = fminf(ylo, sp.ylo);
+        yhi = fmaxf(yhi, sp.yhi);
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
@@ -606,22 +710,39 @@ __device__ __forceinline__ void seed_finish(const HullArgs& a)
         if (lex_beats(false, o0, mn)) mn = o0;
         if (lex_beats(true, o1, mx)) mx = o1;
         bad |= __shfl_xor(bad, m);
+        ylo = fminf(ylo, __shfl_xor(ylo, m));
+        yhi = fmaxf(yhi, __shfl_xor(yhi, m));
     }
-    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = bad; }
+    __shared__ float s_y[2][kSWaves];
+    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = bad; s_y[0][w] = ylo; s_y[1][w] = yhi; }
     __syncthreads();
     if (t == 0) {
         Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
         int qb = s_bad[0];
+        float y0 = s_y[0][0], y1 = s_y[1][0];
         for (int u = 1; u < kSWaves; ++u) {
             if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
             if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
             qb |= s_bad[u];
+            y0 = fminf(y0, s_y[0][u]);
+            y1 = fmaxf(y1, s_y[1][u]);
         }
         SeedPart r;
         r.mnx = q0.x; r.mny = q0.y; r.mni = q0.id;
         r.mxx = q1.x; r.mxy = q1.y; r.mxi = q1.id;
-        r.bad = qb; r.pad = 0;
+        r.bad = qb;
+        r.ylo = y0; r.yhi = y1;
+        // the line filter needs |coordinates| <= 2^60, and pays off when the
+        // input is not far from the origin compared with its extent (its
+        // bound grows with the coordinates, the orientation filter's with
+        // the offsets)
+        r.Mx = fmaxf(fabsf(q0.x), fabsf(q1.x));
+        r.My = fmaxf(fabsf(y0), fabsf(y1));
+        const float ext = fmaxf(q1.x - q0.x, y1 - y0);
+        r.line = (a.line_ok && !a.fp64 && !qb && fmaxf(r.Mx, r.My) <= kLineCoordMax && r.Mx <= 8.0f * ext &&
+                  r.My <= 8.0f * ext) ? 1 : 0;
         gst(&ws->seed_res, r);
+        a.info->stream_line = r.line;
         if (qb) atomicOr(a.err, kErrNonFinite);
         SetInfo si = {};
         si.ax = q0.x; si.ay = q0.y; si.aid = q0.id;
@@ -763,6 +884,7 @@ __global__ __launch_bounds__(kSBlock) void k_sseed(HullArgs a)
     auto* ws = static_cast<StreamWs*>(a.sws);
     if (b == 0 && t == 0) stamp_here(a, 0);
     Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
+    float ylo = INFINITY, yhi = -INFINITY;
     bool bad = false;
     for (int j = b; j < ntiles; j += nb) {
         const int p0 = tile_pair0(j, w) + lane;
@@ -775,7 +897,9 @@ __global__ __launch_bounds__(kSBlock) void k_sseed(HullArgs a)
             for (int h = 0; h < 2; ++h) {
                 const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
                 const bool m = id0 + h < n;
-                bad |= m & !(isfinite(x) & isfinite(y));
+                bad |= m & !((int)isfinite(x) & (int)isfinite(y));
+                ylo = m ? fminf(ylo, y) : ylo;
+                yhi = m ? fmaxf(yhi, y) : yhi;
                 // a lane sees its points in increasing index order: strict
                 // comparisons keep the lowest index among coincident points
                 const bool lt = m & ((x < mn.x) | ((x == mn.x) & (y < mn.y)));
@@ -790,22 +914,29 @@ __global__ __launch_bounds__(kSBlock) void k_sseed(HullArgs a)
         const Lex o0 = shfl_xor_lex(mn, m), o1 = shfl_xor_lex(mx, m);
         if (lex_beats(false, o0, mn)) mn = o0;
         if (lex_beats(true, o1, mx)) mx = o1;
+        ylo = fminf(ylo, __shfl_xor(ylo, m));
+        yhi = fmaxf(yhi, __shfl_xor(yhi, m));
     }
+    __shared__ float s_y[2][kSWaves];
     const int any_bad = __ballot(bad) != 0ull;
-    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = any_bad; }
+    if (lane == 0) { s_lex[0][w] = mn; s_lex[1][w] = mx; s_bad[w] = any_bad; s_y[0][w] = ylo; s_y[1][w] = yhi; }
     __syncthreads();
     if (t == 0) {
         Lex q0 = s_lex[0][0], q1 = s_lex[1][0];
         int qb = s_bad[0];
+        float y0 = s_y[0][0], y1 = s_y[1][0];
         for (int u = 1; u < kSWaves; ++u) {
             if (lex_beats(false, s_lex[0][u], q0)) q0 = s_lex[0][u];
             if (lex_beats(true, s_lex[1][u], q1)) q1 = s_lex[1][u];
             qb |= s_bad[u];
+            y0 = fminf(y0, s_y[0][u]);
+            y1 = fmaxf(y1, s_y[1][u]);
         }
         SeedPart sp;
         sp.mnx = q0.x; sp.mny = q0.y; sp.mni = q0.id;
         sp.mxx = q1.x; sp.mxy = q1.y; sp.mxi = q1.id;
-        sp.bad = qb; sp.pad = 0;
+        sp.bad = qb; sp.line = 0;
+        sp.ylo = y0; sp.yhi = y1; sp.Mx = 0.0f; sp.My = 0.0f;
         gst(&ws->seed[b], sp);
     }
     // clear the first compaction's child cursors (used after this kernel)
@@ -826,9 +957,11 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
     const int ntiles = (n + kSTile - 1) / kSTile;
     const float2* xy = a.xy;
     auto* ws = static_cast<StreamWs*>(a.sws);
-    const SeedPart sr = gld(&ws->seed_res);
+    const SeedPart sr = uni(gld(&ws->seed_res));
     if (sr.bad || (sr.mnx == sr.mxx && sr.mny == sr.mxy)) return;  // finished by the seed
     const float ax = sr.mnx, ay = sr.mny, bx = sr.mxx, by = sr.mxy;
+    const bool line = sr.line && !fp64;
+    const LineF L = make_line(ax, ay, bx, by, sr.Mx, sr.My);
     SplitLane s;
     s.q0 = lc_none(); s.q1 = lc_none();
     s.c0 = 0; s.c1 = 0;
@@ -839,26 +972,50 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
         float4 v[kSRows];
         load_rows(xy, n, p0, tile_pair0(j, w), v);
         // filter-only pass; points needing an exact decision are settled
-        // afterwards, out of line
+        // afterwards, out of line (the pass neither counts nor offers them)
         uint32_t pend = 0u;
+        if (line) {
 #pragma unroll
-        for (int r = 0; r < kSRows; ++r) {
-            const int id0 = 2 * (p0 + 64 * r);
+            for (int r = 0; r < kSRows; ++r) {
+                const int id0 = 2 * (p0 + 64 * r);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
-                const bool m = id0 + h < n;
-                const Orient32 o = orient32p(ax, ay, bx, by, x, y);
-                const int sg = fsign(o, fp64 != 0);
-                // lower side: the area for A->B is -orient; upper: for B->A it is orient
-                const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
-                const float lo = ar - wr, hi = ar + wr;
-                const bool lower = m & (sg < 0), upper = m & (sg > 0);
-                const bool u0 = lc_offer_fast(s.q0, lower, lo, hi, id0 + h, fp64 != 0);
-                const bool u1 = lc_offer_fast(s.q1, upper, lo, hi, id0 + h, fp64 != 0);
-                s.c0 += lower ? 1 : 0;
-                s.c1 += upper ? 1 : 0;
-                pend |= (uint32_t)((m & (sg == 0)) | u0 | u1) << (2 * r + h);
+                for (int h = 0; h < 2; ++h) {
+                    const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
+                    const bool m = id0 + h < n;
+                    const float tt = line_eval(L, x, y);
+                    const bool neg = tt < -L.m, pos = tt > L.m;
+                    // lower side: the area for A->B is -orient; upper: for B->A it is orient
+                    const float ar = neg ? -tt : tt;
+                    const float lo = ar - L.m, hi = ar + L.m;
+                    const bool lower = m & neg, upper = m & pos;
+                    const bool u0 = lc_offer_fast(s.q0, lower, lo, hi, id0 + h, false);
+                    const bool u1 = lc_offer_fast(s.q1, upper, lo, hi, id0 + h, false);
+                    const bool pd = (m & !neg & !pos) | u0 | u1;
+                    s.c0 += (lower & !pd) ? 1 : 0;
+                    s.c1 += (upper & !pd) ? 1 : 0;
+                    pend |= (uint32_t)pd << (2 * r + h);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kSRows; ++r) {
+                const int id0 = 2 * (p0 + 64 * r);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
+                    const bool m = id0 + h < n;
+                    const Orient32 o = orient32p(ax, ay, bx, by, x, y);
+                    const int sg = fsign(o, fp64 != 0);
+                    const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
+                    const float lo = ar - wr, hi = ar + wr;
+                    const bool lower = m & (sg < 0), upper = m & (sg > 0);
+                    const bool u0 = lc_offer_fast(s.q0, lower, lo, hi, id0 + h, fp64 != 0);
+                    const bool u1 = lc_offer_fast(s.q1, upper, lo, hi, id0 + h, fp64 != 0);
+                    const bool pd = (m & (sg == 0)) | u0 | u1;
+                    s.c0 += (lower & !pd) ? 1 : 0;
+                    s.c1 += (upper & !pd) ? 1 : 0;
+                    pend |= (uint32_t)pd << (2 * r + h);
+                }
             }
         }
         n_orient += lane_points(n, p0, tile_pair0(j, w));
@@ -885,7 +1042,9 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
 // therefore that of the reservations, which no later step depends on (every
 // decision is geometric, with index tie-breaks). The last workgroup to finish
 // writes the first pass's segment table.
-__global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
+// The first compaction for one filter mode (LINE: the static line filter).
+template <bool LINE>
+__device__ __forceinline__ void sfirst_body(const HullArgs& a)
 {
     __shared__ int s_wcnt[kSWaves][4];  // per-wave child counts of the current tile
     __shared__ int s_wbase[kSWaves][4]; // ... as offsets inside the tile's reservation
@@ -896,26 +1055,31 @@ __global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
     const int n = a.N;
     const int ntiles = (n + kSTile - 1) / kSTile;
     const float2* xy = a.xy;
+    float* X = a.X[0];
+    float* Y = a.Y[0];
+    int* I = a.I[0];
     auto* ws = static_cast<StreamWs*>(a.sws);
-    const SeedPart sr = gld(&ws->seed_res);
+    const SeedPart sr = uni(gld(&ws->seed_res));
     if (sr.bad || (sr.mnx == sr.mxx && sr.mny == sr.mxy)) return;  // finished by the seed
     const SplitPart pr = gld(&ws->split_res);
-    const int n_lo = pr.cnt[0], n_up = pr.cnt[1];
+    const int n_lo = uni(pr.cnt[0]), n_up = uni(pr.cnt[1]);
     if (n_lo == 0 && n_up == 0) return;  // finished by the split
     FirstGeo g;
     g.ax = sr.mnx; g.ay = sr.mny; g.bx = sr.mxx; g.by = sr.mxy;
-    g.lx = pr.c[0].x; g.ly = pr.c[0].y; g.ux = pr.c[1].x; g.uy = pr.c[1].y;
+    g.lx = uni(pr.c[0].x); g.ly = uni(pr.c[0].y); g.ux = uni(pr.c[1].x); g.uy = uni(pr.c[1].y);
     // output slot of rank R in child k: obase[k] + R (k even), obase[k] - R (k odd)
     const int obase[4] = {1, n_lo, 2 + n_lo, 1 + n_lo + n_up};
+    LineF L[4];
+    L[0] = n_lo > 0 ? make_line(g.ax, g.ay, g.lx, g.ly, sr.Mx, sr.My) : line_never();
+    L[1] = n_lo > 0 ? make_line(g.lx, g.ly, g.bx, g.by, sr.Mx, sr.My) : line_never();
+    L[2] = n_up > 0 ? make_line(g.bx, g.by, g.ux, g.uy, sr.Mx, sr.My) : line_never();
+    L[3] = n_up > 0 ? make_line(g.ux, g.uy, g.ax, g.ay, sr.Mx, sr.My) : line_never();
     FirstLane s;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s.q[k] = lc_none();
     s.n_orient_exact = 0u;
     s.n_cmp_exact = 0u;
     uint32_t n_orient = 0u;
-    float* X = a.X[0];
-    float* Y = a.Y[0];
-    int* I = a.I[0];
     for (int j = b; j < ntiles; j += nb) {
         const int p0 = tile_pair0(j, w) + lane;
         s.code_lo = 0u;
@@ -928,27 +1092,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
             load_rows(xy, n, p0, tile_pair0(j, w), v);
             // filter-only pass; points needing an exact decision are settled
             // afterwards, one at a time
-            uint32_t pend = 0u;
-#pragma unroll
-            for (int rr = 0; rr < kSRows; ++rr) {
-                const int id0 = 2 * (p0 + 64 * rr);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
-                    const bool m = id0 + h < n;
-                    float ar, wr;
-                    int code = first_fast(g, x, y, m, fp64 != 0, ar, wr);
-                    const float lo = ar - wr, hi = ar + wr;
-                    bool und = code == 15;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) und |= lc_offer_fast(s.q[k], code == k, lo, hi, id0 + h, fp64 != 0);
-                    code = und ? 15 : code;
-                    pend |= (uint32_t)und << (2 * rr + h);
-                    const int sh = 4 * (2 * (rr & 3) + h);
-                    if (rr < 4) s.code_lo |= (uint32_t)code << sh;
-                    else s.code_hi |= (uint32_t)code << sh;
-                }
-            }
+            const uint32_t pend = first_fast_rows<LINE>(s, v, p0, n, g, L, fp64 != 0);
             n_orient += 3u * lane_points(n, p0, tile_pair0(j, w));
             if (__ballot(pend != 0u)) {
                 FirstLane tmp = s;
@@ -1029,6 +1173,16 @@ __global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
     }
 }
 
+// One kernel per filter mode; both are launched, and the one whose mode
+// the seed did not choose returns at once (one body per kernel keeps each
+// within its register budget).
+template <bool LINE>
+__global__ __launch_bounds__(kSBlock, 4) void k_sfirst(HullArgs a)
+{
+    const int line = uni(gld(&reinterpret_cast<const StreamWs*>(a.sws)->seed_res.line));
+    if ((line != 0 && !a.fp64) == LINE) sfirst_body<LINE>(a);
+}
+
 // ========================================================== streaming pass
 // One pass of section 4.4 over a segment table of at most kSPassMaxS
 // segments holding at least kSPassMinV points (the first passes of large
@@ -1054,6 +1208,20 @@ __device__ __forceinline__ int pass_fast(const SSeg& g, float x, float y, bool v
     a = -(in1 ? o1.d : o2.d);
     w = 2.0f * (in1 ? o1.es : o2.es);
     const bool und = (s1 == 0) | ((s1 > 0) & (s2 == 0));
+    return !valid ? 7 : (und ? 15 : (in1 ? 0 : (in2 ? 1 : 7)));
+}
+
+// The same with the line filters of A->C and C->B.
+__device__ __forceinline__ int pass_line(const LineF& L0, const LineF& L1, float x, float y, bool valid, float& a,
+                                         float& w)
+{
+    const float t0 = line_eval(L0, x, y), t1 = line_eval(L1, x, y);
+    const bool in1 = t0 < -L0.m, pos0 = t0 > L0.m;
+    const bool n1 = t1 < -L1.m, p1 = t1 > L1.m;
+    const bool in2 = !in1 & pos0 & n1;
+    const bool und = !in1 & !(pos0 & (n1 | p1));
+    a = in1 ? -t0 : -t1;
+    w = in1 ? L0.m : L1.m;
     return !valid ? 7 : (und ? 15 : (in1 ? 0 : (in2 ? 1 : 7)));
 }
 
@@ -1092,6 +1260,9 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
     const int cur = ld_flag(&ws->state[0]) & 1, pass = ld_flag(&ws->state[1]), nxt = cur ^ 1;
     const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
     if (S <= 0 || S > kSPassMaxS || V <= kSPassMinV || pass >= kMaxInfoPasses) return;  // uniform
+    const SeedPart sr = uni(gld(&ws->seed_res));
+    const bool sline = sr.line && !fp64;
+    const float Mx = sr.Mx, My = sr.My, ext = fmaxf(sr.mxx - sr.mnx, sr.yhi - sr.ylo);
     // the segment table and each segment's first tile
     {
         SSeg g = {};
@@ -1153,19 +1324,42 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
                 x[r] = gld(Xi + p); y[r] = gld(Yi + p); id[r] = gld(Ii + p);
             }
             uint32_t pend = 0u;
+            // the line filter where the segment spans at least 1/16 of the
+            // input's extent (its bound grows with the extent; the
+            // orientation filter's with the distances inside the segment)
+            const bool line = sline && fmaxf(fabsf(g.bx - g.ax), fabsf(g.by - g.ay)) * 16.0f >= ext;
+            if (line) {
+                const LineF L0 = make_line(g.ax, g.ay, g.cx, g.cy, Mx, My);
+                const LineF L1 = make_line(g.cx, g.cy, g.bx, g.by, Mx, My);
 #pragma unroll
-            for (int r = 0; r < kPRows; ++r) {
-                const bool m = full | (q0pos + 64 * r + lane < g.len);
-                float ar, wr;
-                int c = pass_fast(g, x[r], y[r], m, fp64 != 0, ar, wr);
-                const float lo2 = ar - wr, hi2 = ar + wr;
-                bool und = c == 15;
-                und |= lc_offer_fast(q0, c == 0, lo2, hi2, id[r], fp64 != 0);
-                und |= lc_offer_fast(q1, c == 1, lo2, hi2, id[r], fp64 != 0);
-                c = und ? 15 : c;
-                pend |= (uint32_t)und << r;
-                n_orient += m ? 2u : 0u;
-                code |= (uint32_t)c << (4 * r);
+                for (int r = 0; r < kPRows; ++r) {
+                    const bool m = full | (q0pos + 64 * r + lane < g.len);
+                    float ar, wr;
+                    int c = pass_line(L0, L1, x[r], y[r], m, ar, wr);
+                    const float lo2 = ar - wr, hi2 = ar + wr;
+                    bool und = c == 15;
+                    und |= lc_offer_fast(q0, c == 0, lo2, hi2, id[r], false);
+                    und |= lc_offer_fast(q1, c == 1, lo2, hi2, id[r], false);
+                    c = und ? 15 : c;
+                    pend |= (uint32_t)und << r;
+                    n_orient += m ? 2u : 0u;
+                    code |= (uint32_t)c << (4 * r);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < kPRows; ++r) {
+                    const bool m = full | (q0pos + 64 * r + lane < g.len);
+                    float ar, wr;
+                    int c = pass_fast(g, x[r], y[r], m, fp64 != 0, ar, wr);
+                    const float lo2 = ar - wr, hi2 = ar + wr;
+                    bool und = c == 15;
+                    und |= lc_offer_fast(q0, c == 0, lo2, hi2, id[r], fp64 != 0);
+                    und |= lc_offer_fast(q1, c == 1, lo2, hi2, id[r], fp64 != 0);
+                    c = und ? 15 : c;
+                    pend |= (uint32_t)und << r;
+                    n_orient += m ? 2u : 0u;
+                    code |= (uint32_t)c << (4 * r);
+                }
             }
             if (__ballot(pend != 0u)) {
                 const Edge e0 = make_edge(g.ax, g.ay, g.cx, g.cy), e1 = make_edge(g.cx, g.cy, g.bx, g.by);

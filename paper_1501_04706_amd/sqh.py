@@ -32,6 +32,7 @@ SQH_VARIANT_PARTITION = 0
 SQH_VARIANT_SORTED = 1
 SQH_FP32_FILTER = 0
 SQH_FP64_ONLY = 1
+SQH_FP32_SEMISTATIC = 2
 
 _lib = None
 
@@ -76,6 +77,8 @@ class SqhStats(ctypes.Structure):
         ("ms_sort", ctypes.c_double),
         ("sorted_points", ctypes.c_int64),
         ("sort_violations", ctypes.c_int64),
+        ("stream_path", ctypes.c_int64),
+        ("line_filter", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -107,6 +110,8 @@ def load() -> ctypes.CDLL:
     lib.sqh_set_prefilter.restype = c_int
     lib.sqh_set_variant.argtypes = [vp, c_int]
     lib.sqh_set_variant.restype = c_int
+    lib.sqh_set_streaming.argtypes = [vp, c_int]
+    lib.sqh_set_streaming.restype = c_int
     lib.sqh_workspace_bytes.argtypes = [i64, i64]
     lib.sqh_workspace_bytes.restype = ctypes.c_size_t
     lib.sqh_hull.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
@@ -194,6 +199,10 @@ def sqh_set_prefilter(ctx: int, mode: int) -> int:
 
 def sqh_set_variant(ctx: int, variant: int) -> int:
     return load().sqh_set_variant(ctx, variant)
+
+
+def sqh_set_streaming(ctx: int, on: int) -> int:
+    return load().sqh_set_streaming(ctx, on)
 
 
 def sqh_workspace_bytes(n_total: int, n_sets: int = 1) -> int:
@@ -376,6 +385,11 @@ class Hull:
         rc = sqh_set_prefilter(self.ctx, mode)
         if rc != SQH_OK:
             raise SqhError(rc, "sqh_set_prefilter")
+
+    def set_streaming(self, on: bool):
+        rc = sqh_set_streaming(self.ctx, 1 if on else 0)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_set_streaming")
 
     def set_variant(self, variant: int):
         rc = sqh_set_variant(self.ctx, variant)

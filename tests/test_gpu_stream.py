@@ -1,0 +1,170 @@
+"""GPU parity of the streaming path (large single hulls) against the oracle.
+
+Calls on one set of at least 2^20 points run the first phases and the passes
+over few large segments as ordinary launches; these cases check that path
+against the oracle and against the general path, at the size threshold and
+with a ragged tail, in every precision mode, with and without the static line
+filter, where the passes kernel takes over, and on its degenerate inputs.
+Hull index lists are integer results: the bar is bit-exact equality.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_04706_amd import sqh, workloads
+
+pytestmark = pytest.mark.gpu
+
+THRESHOLD = 1 << 20
+
+
+def say(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a HIP device"
+    h = sqh.Hull(0)
+    yield h
+    h.close()
+
+
+def run(H, xy, streaming=True, precision=sqh.SQH_FP32_FILTER):
+    import torch
+    H.set_streaming(streaming)
+    H.set_precision(precision)
+    try:
+        t = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)).to("cuda")
+        h = [int(v) for v in H.hull(t).cpu().numpy()]
+        return h, H.stats()
+    finally:
+        H.set_streaming(True)
+        H.set_precision(sqh.SQH_FP32_FILTER)
+
+
+@pytest.mark.parametrize("n", [THRESHOLD, THRESHOLD + 12345])
+@pytest.mark.parametrize("kind", ["square", "disk", "circle", "grid"])
+def test_stream_matches_general(H, kind, n):
+    say(f"stream vs general: {kind} n={n}")
+    xy = workloads.make(kind, n, 11)
+    want = [int(v) for v in oracle.c_hull(xy)]
+    got, st = run(H, xy)
+    assert st["stream_path"] in (1, 2)
+    assert got == want
+    gen, st = run(H, xy, streaming=False)
+    assert st["stream_path"] == 0
+    assert gen == want
+
+
+def test_below_threshold_takes_general_path(H):
+    say("n = 2^20 - 1")
+    xy = workloads.square(THRESHOLD - 1, 12)
+    got, st = run(H, xy)
+    assert st["stream_path"] == 0
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+
+
+@pytest.mark.parametrize("mode", [sqh.SQH_FP32_FILTER, sqh.SQH_FP32_SEMISTATIC, sqh.SQH_FP64_ONLY])
+def test_stream_precision_modes(H, mode):
+    say(f"precision mode {mode}: square n=2000003")
+    xy = workloads.square(2_000_003, 13)
+    got, st = run(H, xy, precision=mode)
+    assert st["stream_path"] == 1
+    assert st["line_filter"] == (1 if mode == sqh.SQH_FP32_FILTER else 0)
+    if mode == sqh.SQH_FP64_ONLY:
+        # the first compaction charges three tests per point; a point
+        # settled by its first exact test takes fewer
+        assert st["orient_exact"] >= 0.99 * st["orient_evals"]
+    else:
+        assert st["orient_exact"] < 1e-3 * st["orient_evals"]
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+
+
+@pytest.mark.parametrize("case", ["offset", "huge", "tiny", "thin"])
+def test_stream_line_filter_domain(H, case):
+    # inputs where the static line filter must stand aside (far from the
+    # origin compared with the extent; |coordinates| beyond 2^60, with
+    # float32 products still in range), where its bound is all underflow
+    # margin (coordinates near 2^-90, kept normal), and a thin strip that
+    # keeps it
+    say(f"line filter domain: {case}")
+    xy = workloads.disk(THRESHOLD + 77, 14).astype(np.float64)
+    if case == "offset":
+        xy += 4096.0
+    elif case == "huge":
+        xy *= 2.0 ** 62
+    elif case == "tiny":
+        xy[np.abs(xy) < 2.0 ** -30] = 0.0
+        xy *= 2.0 ** -90
+    else:
+        xy[:, 1] *= 2.0 ** -3
+    xy = xy.astype(np.float32)
+    got, st = run(H, xy)
+    assert st["stream_path"] in (1, 2)
+    assert st["line_filter"] == (1 if case in ("tiny", "thin") else 0)
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+
+
+def test_stream_hands_over_to_passes_kernel(H):
+    # a jittered circle keeps almost every point: more than 256 segments
+    # before the streaming passes finish it
+    say("circle n=2000000: passes kernel takes over")
+    xy = workloads.circle(2_000_000, 15)
+    got, st = run(H, xy)
+    assert st["stream_path"] == 2
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+
+
+def test_stream_degenerate(H):
+    n = THRESHOLD + 5
+    cases = {
+        "one position": np.full((n, 2), 0.25, np.float32),
+        "two positions": np.where((np.arange(n) % 3 == 0)[:, None], [1.0, 2.0], [-3.0, 0.5]).astype(np.float32),
+        "collinear": np.stack([np.arange(n) % 1000, 2 * (np.arange(n) % 1000)], 1).astype(np.float32),
+        "vertical": np.stack([np.zeros(n), (np.arange(n) * 7919) % 4096], 1).astype(np.float32),
+        "triangle + interior": np.concatenate(
+            [workloads.square(n - 3, 16) * 0.5 + 0.25, np.array([[0, 0], [1, 0], [0, 1]], np.float32)]),
+    }
+    for name, xy in cases.items():
+        say(f"degenerate: {name}")
+        got, st = run(H, xy)
+        assert st["stream_path"] == 1, name
+        assert got == [int(v) for v in oracle.c_hull(xy)], name
+
+
+def test_unaligned_input_takes_general_path(H):
+    import torch
+    say("input at an 8-byte offset")
+    xy = workloads.square(THRESHOLD + 1, 17)
+    big = torch.zeros((THRESHOLD + 2, 2), dtype=torch.float32, device="cuda")
+    big[1:] = torch.from_numpy(xy).to("cuda")
+    view = big[1:]
+    assert view.data_ptr() % 16 == 8
+    got = [int(v) for v in H.hull(view).cpu().numpy()]
+    assert H.stats()["stream_path"] == 0
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+
+
+@pytest.mark.parametrize("mode", [sqh.SQH_FP32_FILTER, sqh.SQH_FP32_SEMISTATIC])
+@pytest.mark.parametrize("off", [0.0, 4096.0])
+def test_stream_ignores_memory_past_the_end(H, mode, off):
+    # the input sits at the start of a larger buffer whose tail holds points
+    # far outside its hull: a ragged last tile must never take them in
+    import torch
+    n = THRESHOLD + 77
+    say(f"memory past the end: mode {mode} offset {off}")
+    xy = (workloads.disk(n, 18).astype(np.float64) + off).astype(np.float32)
+    big = torch.full((n + 16384, 2), off + 1000.0, dtype=torch.float32, device="cuda")
+    big[:n] = torch.from_numpy(xy).to("cuda")
+    H.set_precision(mode)
+    try:
+        got = [int(v) for v in H.hull(big[:n]).cpu().numpy()]
+        st = H.stats()
+    finally:
+        H.set_precision(sqh.SQH_FP32_FILTER)
+    assert st["stream_path"] == 1
+    assert got == [int(v) for v in oracle.c_hull(xy)]

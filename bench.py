@@ -9,13 +9,23 @@ input already resident in device memory; the call returns the hull size to
 the host, so each step ends synchronised.
 
 Prints one JSON line:
-  value      whole-job throughput in Mpoints/s (n / step time)
-  roofline   the dominant kernel's algorithmic HBM bytes per launch divided
-             by its average launch time (HIP events recorded by the library
-             on the launch stream around every launch, over the timed steps)
-             against the 8 TB/s HBM3E peak
+  value      whole-job throughput in Mpoints/s (n / step time), warm caches
+  roofline   the dominant kernel (largest device time per step): its
+             algorithmic HBM bytes per launch divided by its average launch
+             time, from HIP events the library records on the launch stream
+             before and after every kernel during the timed steps, against
+             the 8 TB/s HBM3E peak; `traffic` is the measured HBM bytes per
+             launch from the committed rocprofv3 counter runs
+  kernels    the same figures for every kernel of the call
+  cold       the same call after writing 1 GiB of scratch before each
+             repetition (the 256 MB last-level cache no longer holds the
+             160 MB input)
+  config3    the adversarial 20M-point workloads (jittered circle, integer
+             grid): time, predicate fallback rates, passes
+  filters    the static line filter against the semi-static filter alone:
+             time and fallback rate per workload
   cpu_baseline  the C oracle (monotone chain, exact predicates) timed on
-             this host on the same input, single thread
+             this host on the same input, on one core and on all cores
 """
 from __future__ import annotations
 
@@ -31,12 +41,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-KERNEL = "k_hull"      # the persistent kernel that runs the whole hull
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+# launch names reported by the library -> the kernel's name in rocprofv3
+PROFILER_NAME = {"k_sfirst<line>": "k_sfirst<true>", "k_sfirst<semistatic>": "k_sfirst<false>"}
 
 
-def kernel_bytes(st: dict, n: int) -> int:
-    """Algorithmic HBM bytes of one hull-kernel launch (one sqh_hull call).
+def call_bytes(st: dict, n: int) -> int:
+    """Algorithmic HBM bytes of one whole sqh_hull call.
 
     seed   reads the (x, y) input once: 8 B/pt
     split  reads it again: 8 B/pt
@@ -53,9 +64,61 @@ def kernel_bytes(st: dict, n: int) -> int:
     return 8 * n + 8 * n + 8 * n + 12 * int(st["first_survivors"]) + pass_bytes
 
 
+def launch_sequence(st: dict, n_spass: int) -> list:
+    """The launches of a plain sqh_hull call, as (name, 0.0) pairs: the
+    streaming path (with n_spass k_spass launches; the passes kernel when the
+    call needed it) or the general path's one hull kernel."""
+    if int(st.get("stream_path", 0)) == 0:
+        names = ["k_reset", "k_hull<plain>"]
+    else:
+        names = ["k_reset", "k_sseed", "k_ssplit", "k_sfirst<line>", "k_sfirst<semistatic>"] + \
+                ["k_spass"] * n_spass + ["k_stail"] + (["k_hull<passes>"] if int(st["stream_path"]) == 2 else [])
+    return [(x, 0.0) for x in names]
+
+
+def launch_bytes(launches: list, st: dict, n: int) -> list:
+    """Algorithmic HBM bytes of each launch of one call on the streaming path
+    (k_sseed, k_ssplit: one read of the input, 8 B/pt; the first compaction:
+    one read plus 12 B per survivor written -- its second read of each tile
+    is meant to hit the cache and is not counted; the k-th k_spass launch:
+    pass k's reads and writes, 12 B per point each way, when it ran that
+    pass; the passes kernel when it ran, else the tail: the rest)."""
+    pts = list(st["pass_points"])[: int(st["passes"])]
+
+    def pass_b(k):
+        nxt = pts[k + 1] if k + 1 < len(pts) else 0
+        return 12 * pts[k] + 12 * nxt
+
+    line = int(st.get("line_filter", 0))
+    fallback = any(name == "k_hull<passes>" for name, _ in launches)
+    out, k_spass, spass_ran = [], 0, 0
+    for name, _ in launches:
+        b = 0
+        if name == "k_hull<plain>":
+            b = call_bytes(st, n)
+        elif name in ("k_sseed", "k_ssplit"):
+            b = 8 * n
+        elif name == "k_sfirst<line>":
+            b = (8 * n + 12 * int(st["first_survivors"])) if line else 0
+        elif name == "k_sfirst<semistatic>":
+            b = 0 if line else 8 * n + 12 * int(st["first_survivors"])
+        elif name == "k_spass":
+            # a streaming pass runs while the table qualifies: >= 1024 points
+            # in at most 256 segments
+            if k_spass < len(pts) and k_spass == spass_ran and pts[k_spass] > 1024 and \
+                    int(st["pass_segments"][k_spass]) <= 256:
+                b = pass_b(k_spass)
+                spass_ran += 1
+            k_spass += 1
+        elif name == "k_hull<passes>" or (name == "k_stail" and not fallback):
+            b = sum(pass_b(k) for k in range(spass_ran, len(pts)))
+        out.append(b)
+    return out
+
+
 def load_traffic(kernel: str):
-    """Measured HBM bytes per launch from the committed rocprofv3 counter
-    summary, if it was taken for the current kernel build."""
+    """Measured HBM bytes per launch of `kernel` (its rocprofv3 name) from the
+    committed counter summary, if it was taken for the current build."""
     try:
         with open(PROFILE_TRAFFIC) as f:
             d = json.load(f)
@@ -89,13 +152,13 @@ def _counter_per_dispatch(run_dir: str, counter: str, name_part: str) -> tuple:
     return sum(per.values()) / len(per), len(per)
 
 
-def write_traffic(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+def write_traffic(kname: str, fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
                   copy_bytes: int = 160_000_000) -> dict:
-    """HBM bytes per launch of the hull kernel from two counter runs
-    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
-    counter reads for a device-to-device copy of copy_bytes in each
-    direction; written to profiles/traffic.json with the build's fingerprint."""
-    kname = "k_hull"
+    """HBM bytes per launch of kernel `kname` (a part of its rocprofv3 name)
+    from two counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+    scaled by what the same counter reads for a device-to-device copy of
+    copy_bytes in each direction; merged into profiles/traffic.json with the
+    build's fingerprint."""
     f_k, nk = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", kname)
     w_k, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", kname)
     f_c, nc = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copy")
@@ -109,8 +172,14 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_writ
         "copy_fetch_kib": round(f_c, 1), "copy_write_kib": round(w_c, 1), "copy_dispatches": nc,
         "fetch_scale": round(ff, 4), "write_scale": round(fw, 4),
     }
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            allrec = json.load(f)
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[kname] = rec
     with open(PROFILE_TRAFFIC, "w") as f:
-        json.dump({KERNEL: rec}, f, indent=1)
+        json.dump(allrec, f, indent=1)
         f.write("\n")
     return rec
 
@@ -300,41 +369,40 @@ def _percentiles(lat_ms):
             "mean_ms": round(float(v.mean()), 3)}
 
 
-def bench_serving(H, sqh, torch, workloads, count: int = 600, pool: int = 48, max_passes: int = 32,
+def bench_serving(H, sqh, torch, workloads, count: int = 2000, warm: int = 200, max_passes: int = 32,
                   seed: int = 5) -> dict:
     """Poisson stream of hull requests (sizes log-uniform in [1e3, 4e6], kinds
-    square/disk/circle) from host memory. The engine (continuous batching)
-    against one sqh_hull per request in arrival order (the plain path), both
-    timed from arrival to the hull indices in host memory."""
+    square/disk/circle): `warm` requests, then `count` fresh ones, each a
+    distinct window of points from pinned host memory. The engine
+    (continuous batching) against one sqh_hull per request in arrival order
+    (the plain path), both timed from arrival to the hull indices in host
+    memory; saturated (everything arrives at once), then Poisson arrivals at
+    0.5 and 0.8 of the engine's saturated rate."""
     import numpy as np
-    rng = np.random.default_rng(seed)
-    sizes = workloads.log_uniform_sizes(rng, pool, 1000, 4_000_000)
-    kinds = ("square", "disk", "circle")
-    which = rng.integers(0, 3, size=pool)
-    child = np.random.SeedSequence(seed).spawn(pool)
-    # request payloads live in pinned host memory, as network receive buffers would
-    sets = [torch.from_numpy(workloads.make(kinds[which[i]], int(sizes[i]),
-                                            int(child[i].generate_state(1)[0]))).pin_memory()
-            for i in range(pool)]
-    pick = rng.integers(0, pool, size=count)
+    kinds_ = ("square", "disk", "circle")
+    hi = 4_000_000
+    # one pinned pool per distribution; a request is a window into one
+    pools = [torch.from_numpy(workloads.make(k, hi, seed + 1 + i)).pin_memory() for i, k in enumerate(kinds_)]
+    kk, ss, nn = workloads.request_windows(warm + count, seed=seed, lo=1000, hi=hi)
+    sets = [pools[int(kk[i])][int(ss[i]):int(ss[i]) + int(nn[i])] for i in range(warm + count)]
     dev = torch.device("cuda", 0)
-
     dev_ms = [0.0]  # device time of the engine's steps
 
-    def run_engine(H_, arrivals):
+    def run_engine(H_, reqs, arrivals):
         # admissions copy on their own stream while the previous step computes
         E = H_.engine(1 << 25, 1024, 1 << 24)
         copy = torch.cuda.Stream()
         dev_ms[0] = 0.0
+        m = len(reqs)
         try:
             res = {}
             done_t = {}
             t0 = time.perf_counter()
             nxt = 0
             inflight = False
-            while len(done_t) < count:
+            while len(done_t) < m:
                 now = time.perf_counter() - t0
-                while nxt < count and arrivals[nxt] <= now and E.admit(sets[pick[nxt]], nxt, stream=copy):
+                while nxt < m and arrivals[nxt] <= now and E.admit(sets[reqs[nxt]], nxt, stream=copy):
                     nxt += 1
                 if inflight:
                     E.finish()
@@ -347,57 +415,56 @@ def bench_serving(H, sqh, torch, workloads, count: int = 600, pool: int = 48, ma
                         done_t[r[0]] = time.perf_counter() - t0
                         res[r[0]] = r[1]
                 inflight = E.launch(max_passes)
-                if not inflight and nxt < count:
+                if not inflight and nxt < m:
                     time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
             wall = max(done_t.values())
-            lat = [(done_t[i] - arrivals[i]) * 1000.0 for i in range(count)]
+            lat = [(done_t[i] - arrivals[i]) * 1000.0 for i in range(m)]
             return wall, lat, res
         finally:
             E.close()
 
-    def run_plain(arrivals):
-        out = torch.empty(4_000_000, dtype=torch.int32, device=dev)
-        H.workspace(4_000_000, 1)
+    out1 = torch.empty(hi, dtype=torch.int32, device=dev)
+    H.workspace(hi, 1)
+
+    def run_plain(reqs, arrivals):
         t0 = time.perf_counter()
         lat = []
         res = {}
-        for i in range(count):
+        for i, q in enumerate(reqs):
             now = time.perf_counter() - t0
             if arrivals[i] > now:
                 time.sleep(arrivals[i] - now)
-            xy = sets[pick[i]].to(dev, non_blocking=True)
-            hv = H.hull(xy, out=out).cpu().numpy()
+            xy = sets[q].to(dev, non_blocking=True)
+            hv = H.hull(xy, out=out1).cpu().numpy()
             t = time.perf_counter() - t0
             lat.append((t - arrivals[i]) * 1000.0)
             res[i] = hv
         return time.perf_counter() - t0, lat, res
 
+    warm_reqs = list(range(warm))
+    reqs = list(range(warm, warm + count))
     zero = np.zeros(count)
-    run_engine(H, zero)  # warm-up
-    runs = []
-    for _ in range(3):  # saturated throughput: median of three runs of each path
-        wall_e, _, res_e = run_engine(H, zero)
-        runs.append((wall_e, dev_ms[0]))
-    wall_e, dev_e = sorted(runs)[1]
+    run_engine(H, warm_reqs, np.zeros(warm))  # warm-up requests
+    run_plain(warm_reqs, np.zeros(warm))
+    wall_e, _, res_e = run_engine(H, reqs, zero)
+    dev_e = dev_ms[0]
     T = count / wall_e
-    walls_p = []
-    for _ in range(3):
-        wall_p, _, res_p = run_plain(zero)
-        walls_p.append(wall_p)
-    wall_p = sorted(walls_p)[1]
+    wall_p, _, res_p = run_plain(reqs, zero)
     Tp = count / wall_p
     same = all(np.array_equal(res_e[i], res_p[i]) for i in range(count))
     H64 = sqh.Hull(0, precision=sqh.SQH_FP64_ONLY)
     try:
-        wall_64, _, res_64 = run_engine(H64, zero)
+        wall_64, _, res_64 = run_engine(H64, reqs, zero)
     finally:
         H64.close()
     same64 = all(np.array_equal(res_e[i], res_64[i]) for i in range(count))
+    pts = int(sum(int(nn[q]) for q in reqs))
     out = {
-        "workload": f"{count} requests drawn from {pool} point sets, sizes log-uniform in [1e3, 4e6], "
-                    f"square/disk/circle, seed {seed}, pinned host input, {max_passes} passes per engine step",
+        "workload": f"{warm} warm-up then {count} requests, each a distinct window of a 4M-point pool per "
+                    f"distribution (square/disk/circle), sizes log-uniform in [1e3, 4e6], seed {seed}, "
+                    f"pinned host input, {max_passes} passes per engine step",
+        "points": pts,
         "saturated_hulls_per_s": round(T, 1),
-        "saturated_runs": 3,
         "plain_saturated_hulls_per_s": round(Tp, 1),
         "speedup_vs_plain": round(T / Tp, 2),
         "engine_device_ms": round(dev_e, 1),
@@ -412,49 +479,147 @@ def bench_serving(H, sqh, torch, workloads, count: int = 600, pool: int = 48, ma
         lam = frac * T
         gaps = np.random.default_rng(seed + 1).exponential(1.0 / lam, size=count)
         arr = np.cumsum(gaps)
-        _, lat_e, _ = run_engine(H, arr)
-        _, lat_p, _ = run_plain(arr)
+        _, lat_e, _ = run_engine(H, reqs, arr)
+        _, lat_p, _ = run_plain(reqs, arr)
         out[f"qps_{frac}T"] = round(lam, 1)
         out[f"engine_{frac}T"] = _percentiles(lat_e)
         out[f"plain_{frac}T"] = _percentiles(lat_p)
+    del out1
     return out
 
 
-def release_device(torch) -> None:
-    """Reset the HIP device (end of process)."""
-    import ctypes
+def timed_calls(H, xy_d, out, n: int, steps: int, warmup: int, scratch=None, only=None) -> dict:
+    """`steps` sqh_hull calls (after `warmup` untimed ones) with per-launch
+    events on. Each call returns synchronised; wall_ms is the mean time
+    inside the calls, loop_ms the mean including the reading of the stats
+    and launch times between calls. With `scratch`, 1 GiB of it is
+    rewritten before each call (outside the call's time). With `only`,
+    events bracket only that kernel's launches."""
+    import torch
+    H.set_launch_timing(True, only)
+    for _ in range(warmup):
+        H.hull(xy_d, out=out)
     torch.cuda.synchronize()
-    ctypes.CDLL("libamdhip64.so").hipDeviceReset()
+    keys = ("ms_total", "ms_kernel", "ms_seed", "ms_split", "ms_first", "ms_pass", "ms_emit")
+    agg = {k: 0.0 for k in keys}
+    per = {}  # kernel -> [ms, launches, bytes]
+    exact = evals = cmpx = 0
+    totals = []
+    last = None
+    wall = 0.0
+    torch.cuda.synchronize()
+    l0 = time.perf_counter()
+    for r in range(steps):
+        if scratch is not None:
+            scratch.fill_(float(r))
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.hull(xy_d, out=out)
+        wall += time.perf_counter() - t0
+        st = H.stats()
+        lt = H.launch_times()
+        if only:
+            # the byte model follows the call's whole launch sequence
+            seq = launch_sequence(st, len(lt) if only == "k_spass" else 0)
+            bl = [b for (x, _), b in zip(seq, launch_bytes(seq, st, n)) if x == only]
+        else:
+            bl = launch_bytes(lt, st, n)
+        for name, b, (_, ms) in zip((x for x, _ in lt), bl, lt):
+            e = per.setdefault(name, [0.0, 0, 0])
+            e[0] += ms
+            e[1] += 1
+            e[2] += b
+        for k in agg:
+            agg[k] += st[k]
+        totals.append(st["ms_total"])
+        evals += st["orient_evals"]
+        exact += st["orient_exact"]
+        cmpx += st["cmp_exact"]
+        last = st
+    torch.cuda.synchronize()
+    loop = time.perf_counter() - l0
+    H.set_launch_timing(False)
+    return {"wall_ms": wall * 1000.0 / steps, "loop_ms": loop * 1000.0 / steps, "agg": {k: v / steps for k, v in agg.items()}, "per": per,
+            "totals": totals, "evals": evals, "exact": exact, "cmpx": cmpx, "last": last, "steps": steps}
+
+
+def kernel_table(m: dict) -> dict:
+    """Per-kernel device time per call, average launch time, algorithmic
+    bytes per launch and the bandwidth they imply."""
+    steps = m["steps"]
+    rows = {}
+    for name, (ms, nl, b) in m["per"].items():
+        avg = ms / nl
+        bpl = b / nl
+        rows[name] = {"ms_per_call": round(ms / steps, 4), "launches_per_call": round(nl / steps, 2),
+                      "avg_launch_ms": round(avg, 5), "alg_bytes_per_launch": int(bpl),
+                      "GB_s": round(bpl / (avg / 1000.0) / 1e9, 1) if avg > 0 else 0.0}
+    return rows
+
+
+def filter_modes(H, sqh, torch, workloads, n: int, steps: int = 3, warmup: int = 1) -> dict:
+    """The adversarial workloads and the square under both float32 filter
+    modes: time per call and the predicates' exact-path rates."""
+    dev = torch.device("cuda", 0)
+    res = {}
+    for kind in ("square", "circle", "grid"):
+        xy_d = torch.from_numpy(workloads.make(kind, n, 0)).to(dev)
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+        H.workspace(n, 1)
+        row = {}
+        for name, mode in (("fp32_filter", sqh.SQH_FP32_FILTER), ("fp32_semistatic", sqh.SQH_FP32_SEMISTATIC)):
+            H.set_precision(mode)
+            m = timed_calls(H, xy_d, out, n, steps, warmup, only="-")  # (no kernel has that name: no events)
+            st = m["last"]
+            row[name] = {
+                "ms_per_call": round(m["wall_ms"], 4),
+                "device_ms_per_call": round(m["agg"]["ms_total"], 4),
+                "Mpoints_per_s": round(n / (m["wall_ms"] / 1000.0) / 1e6, 1),
+                "orient_fallback_rate": m["exact"] / m["evals"] if m["evals"] else 0.0,
+                "orient_exact_per_call": m["exact"] // steps,
+                "cmp_exact_per_call": m["cmpx"] // steps,
+                "line_filter": int(st["line_filter"]),
+                "stream_path": int(st["stream_path"]),
+                "passes": int(st["passes"]),
+                "max_segments": int(st["max_segments"]),
+                "hull_size": int(st["hull_size"]),
+            }
+        H.set_precision(sqh.SQH_FP32_FILTER)
+        f, s_ = row["fp32_filter"]["ms_per_call"], row["fp32_semistatic"]["ms_per_call"]
+        row["faster"] = "fp32_filter" if f <= s_ else "fp32_semistatic"
+        res[kind] = row
+        del xy_d, out
+    return res
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=20_000_000)
     ap.add_argument("--kind", default="square", choices=["square", "disk", "circle", "grid"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
-                    help="fp32: float32 filter with exact fallback; fp64: every predicate exact")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32-semistatic", "fp64"],
+                    help="fp32: float32 filters with exact fallback (the static line filter where it "
+                         "applies); fp32-semistatic: without the line filter; fp64: every predicate exact")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=600, help="serving requests (0: skip)")
+    ap.add_argument("--serve", type=int, default=2000, help="serving requests after 200 warm-up (0: skip)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-phase breakdown over sizes and pre-filter modes")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the cold-cache leg, the adversarial workloads and the filter comparison")
     ap.add_argument("--batch", default="64M", choices=["64M", "full", "none"],
                     help="batched comparison: 4096 sets rescaled to ~64M points, the literal "
                          "log-uniform sizes (~4.4e8 points), or skip it")
-    ap.add_argument("--release-device", action="store_true",
-                    help="reset the HIP device before exiting (lets a profiler that wraps this "
-                         "process write its results before it tears down)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of the 20M-point input "
                          "(160 MB read + 160 MB written per launch), to scale HBM counters")
-    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+    ap.add_argument("--write-traffic", nargs=5, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
                                                           "COPY_WRITE_DIR"),
                     help="no GPU work: turn four rocprofv3 --pmc result directories (FETCH_SIZE and "
-                         "WRITE_SIZE of this bench, then of --copy-calibration) into "
-                         "profiles/traffic.json")
+                         "WRITE_SIZE of this bench, then of --copy-calibration) into KERNEL's entry "
+                         "of profiles/traffic.json")
     args = ap.parse_args()
 
     if args.write_traffic:
@@ -467,7 +632,6 @@ def main() -> int:
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
     from paper_1501_04706_amd import sqh, workloads
 
@@ -480,44 +644,29 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "launches": args.warmup + args.steps}), flush=True)
-        del src, dst
-        if args.release_device:
-            release_device(torch)
         return 0
     xy = workloads.make(args.kind, args.n, args.seed)
     xy_d = torch.from_numpy(xy).to(dev)
     H = sqh.Hull(0)
-    if args.precision == "fp64":
-        H.set_precision(sqh.SQH_FP64_ONLY)
+    H.set_precision({"fp32": sqh.SQH_FP32_FILTER, "fp32-semistatic": sqh.SQH_FP32_SEMISTATIC,
+                     "fp64": sqh.SQH_FP64_ONLY}[args.precision])
     out = torch.empty(max(args.n, 1), dtype=torch.int32, device=dev)
     H.workspace(args.n, 1)
-    for _ in range(args.warmup):
-        H.hull(xy_d, out=out)
-    torch.cuda.synchronize()
 
-    keys = ("ms_total", "ms_kernel", "ms_seed", "ms_split", "ms_first", "ms_pass", "ms_emit")
-    agg = {k: 0.0 for k in keys}
-    exact = evals = cmpx = 0
-    last = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        h = H.hull(xy_d, out=out)
-        st = H.stats()
-        for k in agg:
-            agg[k] += st[k]
-        evals += st["orient_evals"]
-        exact += st["orient_exact"]
-        cmpx += st["cmp_exact"]
-        last = st
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1000.0 / args.steps
+    # every kernel's time from an event pair around each launch (these
+    # events cost device time, so these steps are not the timed region)
+    mk = timed_calls(H, xy_d, out, args.n, args.steps, args.warmup)
+    kernels = kernel_table(mk)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_call"])
+    # the timed region: K calls, HIP events on the launch stream around the
+    # dominant kernel's launches only
+    m = timed_calls(H, xy_d, out, args.n, args.steps, 2, only=dom)
+    ms_step = m["wall_ms"]
     value = args.n / (ms_step / 1000.0) / 1e6
-
-    nbytes = kernel_bytes(last, args.n)
-    avg_launch_ms = agg["ms_kernel"] / args.steps
-    achieved = nbytes / (avg_launch_ms / 1000.0) / 1e9
-    traffic = load_traffic(KERNEL)
+    last = m["last"]
+    dk = kernel_table(m)[dom]
+    achieved = dk["GB_s"]
+    traffic = load_traffic(PROFILER_NAME.get(dom, dom))
 
     line = {
         "metric": "Mpoints/s + HBM GB/s (20M-pt hull); batched hulls/s & p99 latency vs plain",
@@ -537,26 +686,58 @@ def main() -> int:
                    "precision": args.precision},
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNEL,
-            "achieved": round(achieved, 1),
+            "kernel": dom,
+            "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "alg_bytes_per_launch": int(nbytes),
-            "avg_launch_ms": round(avg_launch_ms, 5),
+            "alg_bytes_per_launch": dk["alg_bytes_per_launch"],
+            "avg_launch_ms": dk["avg_launch_ms"],
+            "launches": int(m["per"][dom][1]),
         },
+        "kernels": {"note": "separate steps with an event pair around every launch", **kernels},
         "detail": {
             "hull_size": int(last["hull_size"]),
             "passes": int(last["passes"]),
-            "ms_per_call": {k[3:]: round(v / args.steps, 4) for k, v in agg.items()},
+            "stream_path": int(last["stream_path"]),
+            "line_filter": int(last["line_filter"]),
+            "device_ms_per_call": {k[3:]: round(v, 4) for k, v in m["agg"].items()},
+            "ms_per_step_with_bookkeeping": round(m["loop_ms"], 4),
+            "device_ms_median": round(statistics.median(m["totals"]), 4),
+            "device_ms_min": round(min(m["totals"]), 4),
+            "call_alg_bytes": call_bytes(last, args.n),
+            "call_GB_s": round(call_bytes(last, args.n) / (statistics.median(m["totals"]) / 1000.0) / 1e9, 1),
             "one_read_floor_frac": round(8 * args.n / (ms_step / 1000) / 1e9 / HBM_PEAK_GBS, 4),
-            "orient_fallback_rate": (exact / evals) if evals else 0.0,
-            "orient_evals_per_call": evals / args.steps,
-            "cmp_exact_per_call": cmpx / args.steps,
+            "orient_fallback_rate": (m["exact"] / m["evals"]) if m["evals"] else 0.0,
+            "orient_evals_per_call": m["evals"] / args.steps,
+            "cmp_exact_per_call": m["cmpx"] / args.steps,
             "pass_points": list(last["pass_points"])[: int(last["passes"])],
+            "pass_segments": list(last["pass_segments"])[: int(last["passes"])],
+            "pass_ms": [round(v, 4) for v in list(last["pass_ms"])[: int(last["passes"])]],
         },
     }
+    if not args.no_extra:
+        # cold: 1 GiB of scratch rewritten before each call
+        scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        mc = timed_calls(H, xy_d, out, args.n, 10, 2, scratch=scratch, only=dom)
+        del scratch
+        kc = kernel_table(mc)
+        med = statistics.median(mc["totals"])
+        line["cold"] = {
+            "repetitions": 10,
+            "scratch_bytes": 1 << 30,
+            "device_ms_median": round(med, 4),
+            "device_ms_min": round(min(mc["totals"]), 4),
+            "Mpoints_per_s": round(args.n / (med / 1000.0) / 1e6, 1),
+            "call_GB_s": round(call_bytes(mc["last"], args.n) / (med / 1000.0) / 1e9, 1),
+            "dominant_kernel": {"kernel": dom, **kc.get(dom, {}),
+                                "frac": round(kc.get(dom, {}).get("GB_s", 0.0) / HBM_PEAK_GBS, 4)},
+        }
+        filt = filter_modes(H, sqh, torch, workloads, args.n)
+        line["filters"] = filt
+        line["config3"] = {k: {"workload": f"{k}, n={args.n}, seed 0", **filt[k]["fp32_filter"]}
+                           for k in ("circle", "grid")}
     if args.batch != "none":
         line["batched"] = bench_batched(H, sqh, torch, workloads,
                                         64_000_000 if args.batch == "64M" else None,
@@ -571,9 +752,9 @@ def main() -> int:
     else:
         line["cpu_baseline"] = None
     H.close()
+    del xy_d, out
+    torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
-    if args.release_device:
-        release_device(torch)
     return 0
 
 

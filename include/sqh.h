@@ -393,6 +393,25 @@ int sqh_engine_status(const sqh_engine *engine, int64_t *resident, int64_t *stag
 /* Counters of the last hull call on this context. */
 int sqh_get_stats(const sqh_ctx *ctx, sqh_stats *out);
 
+/*
+ * Per-launch device times. With on != 0, every later sqh_hull or
+ * sqh_hull_batched call on this context records a HIP event on its stream
+ * before and after each kernel it launches (the workspace reset included),
+ * or, when `only` names a kernel (as sqh_get_launch_times reports it), only
+ * around that kernel's launches (each event costs device time between the
+ * kernels). Returns SQH_OK, SQH_EINVAL (null ctx, name of 32 characters or
+ * more) or SQH_EDEVICE.
+ */
+int sqh_set_launch_timing(sqh_ctx *ctx, int on, const char *only);
+
+/*
+ * The kernels of the last call (launch timing on), in launch order: up to
+ * cap entries of a static name and the milliseconds between its two events.
+ * A kernel that found nothing to do still appears. Returns the number of
+ * entries, or SQH_EINVAL / SQH_EDEVICE.
+ */
+int sqh_get_launch_times(const sqh_ctx *ctx, const char **names, double *ms, int cap);
+
 /* Diagnostics: with the environment variable SQH_TRACE=1 set before
  * sqh_create, every call records per-workgroup timestamps (100 MHz device
  * clock) at phase boundaries; this copies up to max_entries of them

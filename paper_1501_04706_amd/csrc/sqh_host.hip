@@ -158,6 +158,14 @@ struct sqh_ctx {
     int variant = 0;      // SQH_VARIANT_*
     int stream = 1;       // large single hulls take the streaming path (SQH_STREAM=0 turns it off)
     int spass_used[64];   // per size class: streaming passes the last call ran (-1: none yet)
+    // per-launch timing (sqh_set_launch_timing): events before and after
+    // each kernel of the last call, and the kernels' names
+    static constexpr int kMaxTimed = 24;
+    int ltiming = 0;
+    char lonly[32] = {};  // time only the launches of this kernel ("": all)
+    int nl = 0;
+    hipEvent_t lev[2 * kMaxTimed] = {};
+    const char* lname[kMaxTimed] = {};
     sqh_ctx() { for (int& v : spass_used) v = -1; }
 };
 
@@ -331,19 +339,64 @@ inline dim3 launch_block(const Launch& l)
     return dim3(l.coop || l.f == reinterpret_cast<const void*>(k_stail) ? kBlock : kSBlock);
 }
 
-// Enqueue the workspace reset and the cooperative launches, bracketed by events.
+const char* kernel_name(const void* f)
+{
+    struct { const void* f; const char* name; } const names[] = {
+        {reinterpret_cast<const void*>(k_sseed), "k_sseed"},
+        {reinterpret_cast<const void*>(k_ssplit), "k_ssplit"},
+        {reinterpret_cast<const void*>(k_sfirst<true>), "k_sfirst<line>"},
+        {reinterpret_cast<const void*>(k_sfirst<false>), "k_sfirst<semistatic>"},
+        {reinterpret_cast<const void*>(k_spass), "k_spass"},
+        {reinterpret_cast<const void*>(k_stail), "k_stail"},
+        {reinterpret_cast<const void*>(k_hull<kHullPlain>), "k_hull<plain>"},
+        {reinterpret_cast<const void*>(k_hull<kHullPre>), "k_hull<prefiltered>"},
+        {reinterpret_cast<const void*>(k_hull<kHullFirst>), "k_hull<first>"},
+        {reinterpret_cast<const void*>(k_hull<kHullPasses>), "k_hull<passes>"},
+        {reinterpret_cast<const void*>(k_prefilter), "k_prefilter"},
+        {reinterpret_cast<const void*>(k_sort), "k_sort"},
+    };
+    for (const auto& e : names)
+        if (e.f == f) return e.name;
+    return "?";
+}
+
+// Per-launch timing: an event before and one after each timed kernel.
+inline bool timed(const sqh_ctx* ctx, const char* name)
+{
+    return ctx->ltiming && ctx->nl < sqh_ctx::kMaxTimed && (!ctx->lonly[0] || strcmp(ctx->lonly, name) == 0);
+}
+inline int time_open(sqh_ctx* ctx, const char* name, hipStream_t st)
+{
+    if (timed(ctx, name)) HIP_OK(hipEventRecord(ctx->lev[2 * ctx->nl], st));
+    return SQH_OK;
+}
+inline int time_close(sqh_ctx* ctx, const char* name, hipStream_t st)
+{
+    if (timed(ctx, name)) {
+        HIP_OK(hipEventRecord(ctx->lev[2 * ctx->nl + 1], st));
+        ctx->lname[ctx->nl++] = name;
+    }
+    return SQH_OK;
+}
+
+// Enqueue the workspace reset and the launches, bracketed by events.
 int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st, bool fallback = true)
 {
+    ctx->nl = 0;
     HIP_OK(hipEventRecord(ctx->ev0, st));
+    if (time_open(ctx, "k_reset", st) != SQH_OK) return SQH_EDEVICE;
     k_reset<<<reset_grid, 256, 0, st>>>(a);
     HIP_OK(hipGetLastError());
+    if (time_close(ctx, "k_reset", st) != SQH_OK) return SQH_EDEVICE;
     HIP_OK(hipEventRecord(ctx->evk, st));
     void* argv[] = {static_cast<void*>(&a)};
     Launch L[kMaxLaunches];
     const int nf = call_launches(a, L, fallback);
     for (int i = 0; i < nf; ++i) {
+        if (time_open(ctx, kernel_name(L[i].f), st) != SQH_OK) return SQH_EDEVICE;
         if (L[i].coop) HIP_OK(hipLaunchCooperativeKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
         else HIP_OK(hipLaunchKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
+        if (time_close(ctx, kernel_name(L[i].f), st) != SQH_OK) return SQH_EDEVICE;
     }
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return SQH_OK;
@@ -448,8 +501,10 @@ int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const i
     ctx->spass_used[cls] = (done && hi.spass_n < a.spasses) ? hi.spass_n : kStreamPassLaunches;
     if (done) return rc;
     void* argv[] = {static_cast<void*>(&a)};
+    if (time_open(ctx, "k_hull<passes>", st) != SQH_OK) return SQH_EDEVICE;
     HIP_OK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_hull<kHullPasses>), dim3(tu.grid),
                                       dim3(kBlock), argv, 0, st));
+    if (time_close(ctx, "k_hull<passes>", st) != SQH_OK) return SQH_EDEVICE;
     HIP_OK(hipEventRecord(ctx->ev1, st));
     return collect(ctx, a, N, out_cap, h_total, st, true);
 }
@@ -685,6 +740,8 @@ int sqh_create(sqh_ctx** out, int device)
 void sqh_destroy(sqh_ctx* c)
 {
     if (!c) return;
+    for (hipEvent_t& e : c->lev)
+        if (e) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->evk) (void)hipEventDestroy(c->evk);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1292,6 +1349,33 @@ int sqh_get_trace(const sqh_ctx* c, uint64_t* out, int max_entries)
     if (!c->trace) return 0;
     const int n = std::min(max_entries, c->max_grid * 8);
     for (int i = 0; i < n; ++i) out[i] = c->hinfo->trace[i / 8][i % 8];
+    return n;
+}
+
+int sqh_set_launch_timing(sqh_ctx* c, int on, const char* only)
+{
+    if (!c || (only && strlen(only) >= sizeof c->lonly)) return SQH_EINVAL;
+    if (on && !c->lev[0]) {
+        (void)hipSetDevice(c->device);
+        for (hipEvent_t& e : c->lev)
+            if (hipEventCreate(&e) != hipSuccess) return SQH_EDEVICE;
+    }
+    c->ltiming = on != 0;
+    snprintf(c->lonly, sizeof c->lonly, "%s", only ? only : "");
+    c->nl = 0;
+    return SQH_OK;
+}
+
+int sqh_get_launch_times(const sqh_ctx* c, const char** names, double* ms, int cap)
+{
+    if (!c || cap < 0 || (cap > 0 && (!names || !ms))) return SQH_EINVAL;
+    const int n = std::min(cap, c->nl);
+    for (int i = 0; i < n; ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->lev[2 * i], c->lev[2 * i + 1]) != hipSuccess) return SQH_EDEVICE;
+        names[i] = c->lname[i];
+        ms[i] = t;
+    }
     return n;
 }
 

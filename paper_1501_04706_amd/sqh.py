@@ -112,6 +112,11 @@ def load() -> ctypes.CDLL:
     lib.sqh_set_variant.restype = c_int
     lib.sqh_set_streaming.argtypes = [vp, c_int]
     lib.sqh_set_streaming.restype = c_int
+    lib.sqh_set_launch_timing.argtypes = [vp, c_int, ctypes.c_char_p]
+    lib.sqh_set_launch_timing.restype = c_int
+    lib.sqh_get_launch_times.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                         c_int]
+    lib.sqh_get_launch_times.restype = c_int
     lib.sqh_workspace_bytes.argtypes = [i64, i64]
     lib.sqh_workspace_bytes.restype = ctypes.c_size_t
     lib.sqh_hull.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
@@ -203,6 +208,19 @@ def sqh_set_variant(ctx: int, variant: int) -> int:
 
 def sqh_set_streaming(ctx: int, on: int) -> int:
     return load().sqh_set_streaming(ctx, on)
+
+
+def sqh_set_launch_timing(ctx: int, on: int, only: str | None = None) -> int:
+    return load().sqh_set_launch_timing(ctx, on, only.encode() if only else None)
+
+
+def sqh_get_launch_times(ctx: int, cap: int = 32) -> list:
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = load().sqh_get_launch_times(ctx, names, ms, cap)
+    if n < 0:
+        raise SqhError(n, "sqh_get_launch_times")
+    return [(names[i].decode(), ms[i]) for i in range(n)]
 
 
 def sqh_workspace_bytes(n_total: int, n_sets: int = 1) -> int:
@@ -385,6 +403,15 @@ class Hull:
         rc = sqh_set_prefilter(self.ctx, mode)
         if rc != SQH_OK:
             raise SqhError(rc, "sqh_set_prefilter")
+
+    def set_launch_timing(self, on: bool, only: str | None = None):
+        rc = sqh_set_launch_timing(self.ctx, 1 if on else 0, only)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_set_launch_timing")
+
+    def launch_times(self) -> list:
+        """[(kernel name, ms)] of the last call, launch timing on."""
+        return sqh_get_launch_times(self.ctx)
 
     def set_streaming(self, on: bool):
         rc = sqh_set_streaming(self.ctx, 1 if on else 0)

@@ -170,3 +170,17 @@ def request_stream(count: int, qps: float, seed: int = 5, lo: int = 1000,
         out.append(Request(float(t[i]), make(kind, int(sizes[i]), int(child[i].generate_state(1)[0])),
                            kind, i))
     return out
+
+
+def request_windows(count: int, seed: int = 5, lo: int = 1000, hi: int = 4_000_000, nkinds: int = 3):
+    """Request recipes for the serving workload without materialising every
+    set: request i takes ``sizes[i]`` consecutive points, from ``starts[i]``,
+    of the ``kinds[i]``-th pool of ``hi`` points (one pool per distribution,
+    drawn once by ``make(kind, hi, seed)``). Sizes are log-uniform in
+    [lo, hi], kinds uniform, starts uniform over the pool; returns three
+    int64 arrays (kinds, starts, sizes)."""
+    rng = np.random.default_rng(seed)
+    sizes = log_uniform_sizes(rng, count, lo, hi).astype(np.int64)
+    kinds = rng.integers(0, nkinds, size=count).astype(np.int64)
+    starts = np.floor(rng.random(count) * (hi - sizes + 1)).astype(np.int64)
+    return kinds, starts, sizes

@@ -20,12 +20,38 @@ def _write_counters(d, rows):
             f.write(",".join(str(v) for v in r) + "\n")
 
 
-def test_kernel_bytes_model():
+def test_call_bytes_model():
     # seed + split + first read 8 B/pt each, first writes 12 B per survivor,
     # pass k reads its points and writes the next pass's
     st = {"pass_points": [100, 10, 0], "passes": 2, "first_survivors": 100}
     n = 1000
-    assert bench.kernel_bytes(st, n) == 24 * n + 12 * 100 + (12 * 100 + 12 * 10) + (12 * 10 + 0)
+    assert bench.call_bytes(st, n) == 24 * n + 12 * 100 + (12 * 100 + 12 * 10) + (12 * 10 + 0)
+
+
+def test_launch_bytes_model():
+    # streaming path: seed and split read the input, the line-filter first
+    # compaction reads it and writes the survivors (the other mode's kernel
+    # returns at once), k_spass launches take the passes over more than 1024
+    # points in at most 256 segments in order, the passes kernel the rest
+    n = 1_000_000
+    st = {"pass_points": [400000, 90000, 3000, 500, 20], "pass_segments": [4, 8, 300, 20, 4], "passes": 5,
+          "first_survivors": 400000, "line_filter": 1}
+    names = ["k_reset", "k_sseed", "k_ssplit", "k_sfirst<line>", "k_sfirst<semistatic>",
+             "k_spass", "k_spass", "k_spass", "k_stail", "k_hull<passes>"]
+    b = bench.launch_bytes([(x, 0.0) for x in names], st, n)
+    p = [12 * (400000 + 90000), 12 * (90000 + 3000), 12 * (3000 + 500), 12 * (500 + 20), 12 * 20]
+    assert b == [0, 8 * n, 8 * n, 8 * n + 12 * 400000, 0, p[0], p[1], 0, 0, p[2] + p[3] + p[4]]
+    st["line_filter"] = 0
+    b = bench.launch_bytes([(x, 0.0) for x in names], st, n)
+    assert b[3] == 0 and b[4] == 8 * n + 12 * 400000
+    # a call's launches add up to the whole call's bytes
+    assert sum(b) == bench.call_bytes(st, n)
+    # no passes kernel: the tail takes the rest
+    st["pass_segments"] = [4, 8, 20, 20, 4]
+    st["pass_points"] = [400000, 90000, 3000, 500, 20]
+    b = bench.launch_bytes([(x, 0.0) for x in names[:-1]], st, n)
+    assert b[5:8] == [p[0], p[1], p[2]] and b[8] == p[3] + p[4]
+    assert sum(b) == bench.call_bytes(st, n)
 
 
 def test_write_traffic_scales_by_copy(tmp_path, monkeypatch):
@@ -45,17 +71,20 @@ def test_write_traffic_scales_by_copy(tmp_path, monkeypatch):
     _write_counters(str(tmp_path / "cf"), [(7, "__amd_rocclr_copyBuffer", "FETCH_SIZE", c),
                                            (8, "elementwise_uniform", "FETCH_SIZE", 5)])
     _write_counters(str(tmp_path / "cw"), [(7, "__amd_rocclr_copyBuffer", "WRITE_SIZE", c)])
-    rec = bench.write_traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+    K = "k_hull<0>"
+    rec = bench.write_traffic(K, str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                              str(tmp_path / "cw"))
     assert rec["dispatches"] == 2 and rec["copy_dispatches"] == 1
     assert rec["fetch_kib"] == pytest.approx(400000.0) and rec["write_kib"] == pytest.approx(60000.0)
     assert rec["bytes_per_launch"] == pytest.approx((400000 + 60000) * kib / 1.1, rel=1e-6)
     saved = json.load(open(tmp_path / "traffic.json"))
-    assert saved[bench.KERNEL]["build"] == bench.library_fingerprint()
+    assert saved[K]["build"] == bench.library_fingerprint()
     # the bench reads it back only for the same kernel sources
-    assert bench.load_traffic(bench.KERNEL) == rec["bytes_per_launch"]
-    saved[bench.KERNEL]["build"] = "0" * 16
+    assert bench.load_traffic(K) == rec["bytes_per_launch"]
+    assert bench.load_traffic("k_other") is None
+    saved[K]["build"] = "0" * 16
     json.dump(saved, open(tmp_path / "traffic.json", "w"))
-    assert bench.load_traffic(bench.KERNEL) is None
+    assert bench.load_traffic(K) is None
 
 
 def _f32(v):

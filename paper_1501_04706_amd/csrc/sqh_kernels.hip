@@ -15,6 +15,7 @@
 //   k_emit    the surviving heads, in ring order, are the hull
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "sqh_pred.hpp"
 #include "sqh_chunk.hpp"

@@ -247,6 +247,7 @@ struct SeedPart {
 // the constants come from the input's extent, once per edge.
 struct LineF {
     float nx, ny, c, m;
+    float m2;  // 2 m: the width of every area interval of this edge
 };
 __device__ __forceinline__ LineF make_line(float ox, float oy, float ex, float ey, float Mx, float My)
 {
@@ -256,13 +257,14 @@ __device__ __forceinline__ LineF make_line(float ox, float oy, float ex, float e
     L.ny = dx;
     L.c = dy * ox - dx * oy;
     L.m = (fabsf(dx) * My + fabsf(dy) * Mx) * kLineRel + kFilterTau;
+    L.m2 = 2.0f * L.m;
     return L;
 }
 // an edge no point is strictly right of (a side without points)
 __device__ __forceinline__ LineF line_never()
 {
     LineF L;
-    L.nx = 0.0f; L.ny = 0.0f; L.c = INFINITY; L.m = 0.0f;
+    L.nx = 0.0f; L.ny = 0.0f; L.c = INFINITY; L.m = 0.0f; L.m2 = 0.0f;
     return L;
 }
 __device__ __forceinline__ float line_eval(const LineF& L, float px, float py)
@@ -431,29 +433,6 @@ __device__ __forceinline__ int first_fast(const FirstGeo& g, float x, float y, b
     return !valid ? 7 : (und ? 15 : (in1 ? b : (in2 ? b + 1 : 7)));
 }
 
-// The same with the line filter of the four edges A->C_lo, C_lo->B, B->C_up,
-// C_up->A: a point belongs to the child whose edge it is strictly right of.
-// This is the rule above: a point right of A->C_lo or C_lo->B is right of
-// A->B (A is the lexicographic minimum, so seen from A every point lies in
-// a half-plane where "clockwise of" orders directions), likewise for the
-// upper edges seen from B, and no point is right of both edges of one side
-// (C is the farthest point). So one certified negative edge decides the
-// child, four certified positive edges discard the point, and anything else
-// is settled exactly.
-__device__ __forceinline__ int first_line(const LineF (&L)[4], float x, float y, bool valid, float& a, float& w)
-{
-    const float t0 = line_eval(L[0], x, y), t1 = line_eval(L[1], x, y);
-    const float t2 = line_eval(L[2], x, y), t3 = line_eval(L[3], x, y);
-    const bool n0 = t0 < -L[0].m, n1 = t1 < -L[1].m, n2 = t2 < -L[2].m, n3 = t3 < -L[3].m;
-    const bool p0 = t0 > L[0].m, p1 = t1 > L[1].m, p2 = t2 > L[2].m, p3 = t3 > L[3].m;
-    const int code = n0 ? 0 : (n1 ? 1 : (n2 ? 2 : (n3 ? 3 : 7)));
-    const float ts = n0 ? t0 : (n1 ? t1 : (n2 ? t2 : t3));
-    w = n0 ? L[0].m : (n1 ? L[1].m : (n2 ? L[2].m : L[3].m));
-    a = -ts;
-    const bool und = !(n0 | n1 | n2 | n3) & !(p0 & p1 & p2 & p3);
-    return !valid ? 7 : (und ? 15 : code);
-}
-
 struct FirstLane {
     LCand q[4];
     uint32_t code_lo, code_hi;
@@ -462,9 +441,8 @@ struct FirstLane {
 
 // Filter-only pass over one wave's rows of a tile: codes (4 bits per point,
 // 15 = settle exactly) and the lanes' candidates; returns the pending mask.
-template <bool LINE>
 __device__ __forceinline__ uint32_t first_fast_rows(FirstLane& s, const float4 (&v)[kSRows], int p0, int n,
-                                                    const FirstGeo& g, const LineF (&L)[4], bool fp64)
+                                                    const FirstGeo& g, bool fp64)
 {
     uint32_t pend = 0u;
 #pragma unroll
@@ -475,12 +453,81 @@ __device__ __forceinline__ uint32_t first_fast_rows(FirstLane& s, const float4 (
             const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
             const bool m = id0 + h < n;
             float ar, wr;
-            int code = LINE ? first_line(L, x, y, m, ar, wr) : first_fast(g, x, y, m, fp64, ar, wr);
+            int code = first_fast(g, x, y, m, fp64, ar, wr);
             const float lo = ar - wr, hi = ar + wr;
             bool und = code == 15;
 #pragma unroll
             for (int k = 0; k < 4; ++k) und |= lc_offer_fast(s.q[k], code == k, lo, hi, id0 + h, fp64);
             code = und ? 15 : code;
+            pend |= (uint32_t)und << (2 * rr + h);
+            const int sh = 4 * (2 * (rr & 3) + h);
+            if (rr < 4) s.code_lo |= (uint32_t)code << sh;
+            else s.code_hi |= (uint32_t)code << sh;
+        }
+    }
+    return pend;
+}
+
+// The first compaction with the line filter of the four edges A->C_lo,
+// C_lo->B, B->C_up, C_up->A: a point belongs to the child whose edge it is
+// strictly right of. This is the side-then-edges rule: a point right of
+// A->C_lo or C_lo->B is right of A->B (A is the lexicographic minimum, so
+// seen from A every point lies in a half-plane where "clockwise of" orders
+// directions), likewise for the upper edges seen from B, and no point is
+// right of both edges of one side (C is the farthest point). So one
+// certified negative edge decides the child, four certified positive edges
+// discard the point, and anything else is settled exactly.
+//
+// Every area interval of one edge has the same width 2m, so a lane keeps,
+// per child, the centre of its candidate's interval: a point wins when its
+// centre is more than 2m above, and is settled exactly when it is within
+// 2m. A point is offered to every child whose edge does not certify it
+// outside (not only to its own): a point that is not in child k has an
+// exact area of at most 0 for k's edge, below every point of the child, so
+// such a candidate only lasts where the lane has no point of the child, and
+// the exact comparisons keep the order right.
+struct LineCand {
+    float c;  // centre of the area interval
+    int id;
+};
+struct FirstLineLane {
+    LineCand q[4];
+    uint32_t code_lo, code_hi;
+    uint32_t n_orient_exact, n_cmp_exact;
+};
+
+__device__ __forceinline__ uint32_t first_line_rows(FirstLineLane& s, const float4 (&v)[kSRows], int p0, int n,
+                                                    const LineF (&L)[4])
+{
+    uint32_t pend = 0u;
+#pragma unroll
+    for (int rr = 0; rr < kSRows; ++rr) {
+        const int id0 = 2 * (p0 + 64 * rr);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float x = h ? v[rr].z : v[rr].x, y = h ? v[rr].w : v[rr].y;
+            const bool m = id0 + h < n;
+            float t[4];
+            bool neg[4], pos[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                t[k] = line_eval(L[k], x, y);
+                neg[k] = t[k] < -L[k].m;
+                pos[k] = t[k] > L[k].m;
+            }
+            int code = neg[0] ? 0 : (neg[1] ? 1 : (neg[2] ? 2 : (neg[3] ? 3 : 7)));
+            bool und = m & !(neg[0] | neg[1] | neg[2] | neg[3]) & !(pos[0] & pos[1] & pos[2] & pos[3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float a = -t[k];
+                const float u = a - s.q[k].c;  // +inf while the lane has no candidate
+                const bool mk = m & !pos[k];
+                const bool win = mk & (u > L[k].m2);
+                und |= mk & !win & (u >= -L[k].m2);
+                s.q[k].c = win ? a : s.q[k].c;
+                s.q[k].id = win ? id0 + h : s.q[k].id;
+            }
+            code = !m ? 7 : (und ? 15 : code);
             pend |= (uint32_t)und << (2 * rr + h);
             const int sh = 4 * (2 * (rr & 3) + h);
             if (rr < 4) s.code_lo |= (uint32_t)code << sh;
@@ -654,6 +701,59 @@ __device__ __forceinline__ void first_pending(FirstLane* st, uint32_t pend, int 
             // the fast pass offered nothing for a pending point
 #pragma unroll
             for (int k = 0; k < 4; ++k) lc_offer(s.q[k], code == k, lo, hi, id, P.x, P.y, E[k], xy, f64, s.n_cmp_exact);
+            const int sh = 4 * (i & 7);
+            if (i < 8) s.code_lo = (s.code_lo & ~(15u << sh)) | ((uint32_t)code << sh);
+            else s.code_hi = (s.code_hi & ~(15u << sh)) | ((uint32_t)code << sh);
+        }
+    }
+    *st = s;
+}
+
+// The pending points of first_line_rows, one at a time: the exact child,
+// and the offer to it with the point's line interval.
+__device__ __forceinline__ void first_pending_line(FirstLineLane* st, uint32_t pend, int p0, FirstGeo g,
+                                                   const LineF (&L)[4], const float2* xy)
+{
+    Edge E[4];
+    E[0] = make_edge(g.ax, g.ay, g.lx, g.ly);
+    E[1] = make_edge(g.lx, g.ly, g.bx, g.by);
+    E[2] = make_edge(g.bx, g.by, g.ux, g.uy);
+    E[3] = make_edge(g.ux, g.uy, g.ax, g.ay);
+    FirstLineLane s = *st;
+#pragma unroll 1
+    for (int i = 0; i < 2 * kSRows; ++i) {
+        const bool mine = (pend >> i) & 1u;
+        if (!__ballot(mine)) continue;
+        if (mine) {
+            const int id = 2 * (p0 + 64 * (i >> 1)) + (i & 1);
+            const float2 P = gld(xy + id);
+            float ar, wr;
+            Counters c = {0u, s.n_orient_exact, 0u};
+            const int code = first_classify(g, P.x, P.y, true, false, ar, wr, c);
+            s.n_orient_exact = c.orient_exact;
+            if (code < 4) {
+                // one comparison, on child `code`'s edge and candidate
+                // (selected, so that the exact code is inlined once)
+                const bool k0 = code == 0, k1 = code == 1, k2 = code == 2;
+                const LineF Lk = k0 ? L[0] : (k1 ? L[1] : (k2 ? L[2] : L[3]));
+                const Edge Ek = k0 ? E[0] : (k1 ? E[1] : (k2 ? E[2] : E[3]));
+                const float qc = k0 ? s.q[0].c : (k1 ? s.q[1].c : (k2 ? s.q[2].c : s.q[3].c));
+                const int qid = k0 ? s.q[0].id : (k1 ? s.q[1].id : (k2 ? s.q[2].id : s.q[3].id));
+                const float a = -line_eval(Lk, P.x, P.y);
+                const float u = a - qc;
+                bool win = u > Lk.m2;
+                if (!win && u >= -Lk.m2) {
+                    const float2 Q = gld(xy + qid);
+                    ++s.n_cmp_exact;
+                    win = beats_exact_xy_inl(Ek, P.x, P.y, id, Q.x, Q.y, qid);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool take = win && code == k;
+                    s.q[k].c = take ? a : s.q[k].c;
+                    s.q[k].id = take ? id : s.q[k].id;
+                }
+            }
             const int sh = 4 * (i & 7);
             if (i < 8) s.code_lo = (s.code_lo & ~(15u << sh)) | ((uint32_t)code << sh);
             else s.code_hi = (s.code_hi & ~(15u << sh)) | ((uint32_t)code << sh);
@@ -1074,9 +1174,17 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     L[1] = n_lo > 0 ? make_line(g.lx, g.ly, g.bx, g.by, sr.Mx, sr.My) : line_never();
     L[2] = n_up > 0 ? make_line(g.bx, g.by, g.ux, g.uy, sr.Mx, sr.My) : line_never();
     L[3] = n_up > 0 ? make_line(g.ux, g.uy, g.ax, g.ay, sr.Mx, sr.My) : line_never();
-    FirstLane s;
+    using Lane = std::conditional_t<LINE, FirstLineLane, FirstLane>;
+    Lane s;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s.q[k] = lc_none();
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (LINE) {
+            s.q[k].c = -INFINITY;
+            s.q[k].id = -1;
+        } else {
+            s.q[k] = lc_none();
+        }
+    }
     s.n_orient_exact = 0u;
     s.n_cmp_exact = 0u;
     uint32_t n_orient = 0u;
@@ -1092,12 +1200,22 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
             load_rows(xy, n, p0, tile_pair0(j, w), v);
             // filter-only pass; points needing an exact decision are settled
             // afterwards, one at a time
-            const uint32_t pend = first_fast_rows<LINE>(s, v, p0, n, g, L, fp64 != 0);
-            n_orient += 3u * lane_points(n, p0, tile_pair0(j, w));
-            if (__ballot(pend != 0u)) {
-                FirstLane tmp = s;
-                first_pending(&tmp, pend, p0, g, xy, fp64);
-                s = tmp;
+            if constexpr (LINE) {
+                const uint32_t pend = first_line_rows(s, v, p0, n, L);
+                n_orient += 4u * lane_points(n, p0, tile_pair0(j, w));
+                if (__ballot(pend != 0u)) {
+                    Lane tmp = s;
+                    first_pending_line(&tmp, pend, p0, g, L, xy);
+                    s = tmp;
+                }
+            } else {
+                const uint32_t pend = first_fast_rows(s, v, p0, n, g, fp64 != 0);
+                n_orient += 3u * lane_points(n, p0, tile_pair0(j, w));
+                if (__ballot(pend != 0u)) {
+                    Lane tmp = s;
+                    first_pending(&tmp, pend, p0, g, xy, fp64);
+                    s = tmp;
+                }
             }
         }
         int wc[4] = {0, 0, 0, 0};
@@ -1161,7 +1279,29 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
         }
         __syncthreads();
     }
-    first_wg_partial(&ws->first[b], s, g, xy, fp64);
+    if constexpr (LINE) {
+        // a candidate the filter did not place strictly right of its edge
+        // may be no point of the child (the offers were not limited to the
+        // child's points): keep it only if the exact test does; then the
+        // candidates as intervals [c - m, c + m]
+        const float ex[5] = {g.ax, g.lx, g.bx, g.ux, g.ax}, ey[5] = {g.ay, g.ly, g.by, g.uy, g.ay};
+        FirstLane f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int id = s.q[k].id;
+            if (id >= 0 && s.q[k].c <= L[k].m) {
+                const float2 P = gld(xy + id);
+                ++s.n_orient_exact;
+                if (orient_exact(ex[k], ey[k], ex[k + 1], ey[k + 1], P.x, P.y) >= 0) id = -1;
+            }
+            f.q[k].lo = s.q[k].c - L[k].m;
+            f.q[k].hi = s.q[k].c + L[k].m;
+            f.q[k].id = id;
+        }
+        first_wg_partial(&ws->first[b], f, g, xy, fp64);
+    } else {
+        first_wg_partial(&ws->first[b], s, g, xy, fp64);
+    }
     Counters ctr = {n_orient, s.n_orient_exact, s.n_cmp_exact};
     flush_counters(a.stats, ctr);
     if (last_arrival(&ws->done[2], nb)) {

@@ -1149,6 +1149,10 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     __shared__ int s_wcnt[kSWaves][4];  // per-wave child counts of the current tile
     __shared__ int s_wbase[kSWaves][4]; // ... as offsets inside the tile's reservation
     __shared__ int s_base[4];          // the tile's first rank in each child
+    // the tile as each thread loaded it, for the scatter (read back only by
+    // the thread that wrote it): held here rather than in registers across
+    // the reservation, and rather than read again from memory
+    __shared__ float4 s_tile[kSRows][kSBlock];
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int fp64 = a.fp64;
@@ -1193,11 +1197,10 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
         s.code_lo = 0u;
         s.code_hi = 0u;  // 4 bits per point i = 2 row + h: rows 0-3 / 4-7
         {
-            // (the tile is loaded twice: here, and for the scatter once its
-            // slots are reserved, when it is still in the L2 cache; holding
-            // it in registers across the reservation would spill)
             float4 v[kSRows];
             load_rows(xy, n, p0, tile_pair0(j, w), v);
+#pragma unroll
+            for (int rr = 0; rr < kSRows; ++rr) s_tile[rr][t] = v[rr];
             // filter-only pass; points needing an exact decision are settled
             // afterwards, one at a time
             if constexpr (LINE) {
@@ -1245,7 +1248,8 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
             // scatter: ranks inside a row from ballots, so that each row
             // writes one contiguous run per child
             float4 v[kSRows];
-            load_rows(xy, n, p0, tile_pair0(j, w), v);
+#pragma unroll
+            for (int rr = 0; rr < kSRows; ++rr) v[rr] = s_tile[rr][t];
             int run[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) run[k] = s_base[k] + s_wbase[w][k];

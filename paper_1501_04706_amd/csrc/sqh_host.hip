@@ -25,8 +25,11 @@ namespace {
 
 constexpr size_t kAlign = 256;
 // Streaming passes enqueued per call: at most kStreamPassLaunches (each does
-// nothing once the segment table no longer qualifies); a context enqueues one
-// more than the previous call of the same size class needed.
+// nothing once the segment table no longer qualifies); a context enqueues as
+// many as the previous call of the same size class needed when the
+// streaming kernels finished that call, else all of them, plus one on few
+// workgroups in case this call needs one more (a call that needs more than
+// it got is finished by the passes kernel).
 constexpr int kStreamPassLaunches = 8;
 constexpr int kMaxLaunches = 16;
 constexpr int kMaxGrid = kMaxChunks;  // workgroups of the persistent kernel (upper bound)
@@ -298,7 +301,9 @@ inline bool pre_runs(const HullArgs& a) { return a.prefilter && a.G == 1 && a.N 
 struct Launch {
     const void* f;
     int coop;
+    int light;  // a streaming pass launched on few workgroups (in case one more is needed)
 };
+constexpr int kLightGrid = 64;
 
 // The streaming path ends with k_stail; the passes kernel follows it in the
 // same sequence when `fallback` is set (graphs), else only when the hull is
@@ -306,13 +311,16 @@ struct Launch {
 inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fallback = true)
 {
     int n = 0;
-    auto add = [&](const void* f, int coop) { L[n].f = f; L[n].coop = coop; ++n; };
+    auto add = [&](const void* f, int coop, int light = 0) {
+        L[n].f = f; L[n].coop = coop; L[n].light = light; ++n;
+    };
     if (a.stream) {
         add(reinterpret_cast<const void*>(k_sseed), 0);
         add(reinterpret_cast<const void*>(k_ssplit), 0);
         add(reinterpret_cast<const void*>(k_sfirst<true>), 0);
         add(reinterpret_cast<const void*>(k_sfirst<false>), 0);
         for (int i = 0; i < a.spasses; ++i) add(reinterpret_cast<const void*>(k_spass), 0);
+        if (!fallback && a.spasses < kStreamPassLaunches) add(reinterpret_cast<const void*>(k_spass), 0, 1);
         add(reinterpret_cast<const void*>(k_stail), 0);
         if (fallback) add(reinterpret_cast<const void*>(k_hull<kHullPasses>), 1);
         return n;
@@ -332,6 +340,7 @@ inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fall
 inline dim3 launch_grid(const Launch& l, int grid)
 {
     if (l.f == reinterpret_cast<const void*>(k_stail)) return dim3(1);
+    if (l.light) return dim3(kLightGrid);
     return dim3(l.coop ? grid : std::min(2 * grid, kMaxSGrid));
 }
 inline dim3 launch_block(const Launch& l)
@@ -491,14 +500,13 @@ int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const i
     }
     // streaming path: the passes kernel only if the streaming kernels left work
     const int cls = std::min(log2_class(N), 63);
-    a.spasses = ctx->spass_used[cls] < 0 ? kStreamPassLaunches
-                                         : std::min(kStreamPassLaunches, ctx->spass_used[cls] + 1);
+    a.spasses = ctx->spass_used[cls] < 0 ? kStreamPassLaunches : ctx->spass_used[cls];
     rc = enqueue(ctx, a, reset_grid, tu.grid, st, false);
     if (rc != SQH_OK) return rc;
     rc = collect(ctx, a, N, out_cap, h_total, st, true);
     const HullInfo& hi = *ctx->hinfo;
     const bool done = hi.stream_done != 0 || *ctx->herr != 0;
-    ctx->spass_used[cls] = (done && hi.spass_n < a.spasses) ? hi.spass_n : kStreamPassLaunches;
+    ctx->spass_used[cls] = hi.stream_done != 0 ? std::min(hi.spass_n, kStreamPassLaunches) : kStreamPassLaunches;
     if (done) return rc;
     void* argv[] = {static_cast<void*>(&a)};
     if (time_open(ctx, "k_hull<passes>", st) != SQH_OK) return SQH_EDEVICE;

@@ -283,7 +283,7 @@ struct FirstPart {
 
 // Per-call state of the streaming path in the workspace.
 constexpr int kSPassMaxS = 256;      // streaming passes take at most this many segments ...
-constexpr int kSPassMinV = kTinyPoints;  // ... and more than this many (fewer: k_stail)
+constexpr int kSPassMinV = 6144;         // ... and more than this many (fewer: k_stail)
 constexpr int kPRows = 8;            // rows of points per wave and tile in a streaming pass
 constexpr int kPTile = kSBlock * kPRows;
 
@@ -1676,6 +1676,326 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
     }
 }
 
+// ---- the last passes of a large hull, in LDS ------------------------------
+//
+// Once at most kLPoints points are left (and few enough segments), one
+// workgroup copies them into LDS and runs the remaining passes there, six
+// points per thread: each point is classified against A->C and C->B of its
+// segment (section 4.4.3) and takes its rank in its child from an LDS
+// counter; the farthest point of each child (section 4.4.1) is found among
+// the points whose area interval reaches the largest lower bound in the
+// child, by exact comparison with a leader (the leader steps down when a
+// candidate beats it, until none does); a block scan places the children
+// (section 4.4.4) and the points move to their child in place (each thread
+// holds its points in registers across the move). Slot ranges and vertex
+// keys follow the global passes exactly (child (A, C) keeps the front of the
+// parent's slots, (C, B) the back, C's key is off + |(A, C)|); inside a child
+// the points keep no order.
+constexpr int kLPoints = 6144;            // at most this many points ...
+constexpr int kLSegs = 1024;              // ... and table entries
+constexpr int kLPer = kLPoints / kBlock;  // points per thread
+static_assert(kSPassMinV == kLPoints, "the streaming passes stop where the LDS passes can start");
+static_assert(kLPoints % kBlock == 0 && kLPoints <= 8192 && kLSegs <= kBlock, "packing and one thread per segment");
+
+struct LSeg {
+    float ax, ay, bx, by, cx, cy;  // A, B and the farthest point C
+    int off, len, cid, vs;         // slot range, C's index, first point in LDS
+};
+struct LTail {
+    float x[kLPoints], y[kLPoints];
+    int id[kLPoints];
+    LSeg seg[kLSegs + 1];         // + the sentinel: seg[S].vs = V
+    int cnt[2 * kLSegs];          // per (segment, child): its points; bit 31: the leader was beaten
+    unsigned key[2 * kLSegs];     // ... the largest lower bound (ordered bits); then the child's first point
+    int lead[2 * kLSegs];         // ... the leading candidate (a position)
+    float la[2 * kLSegs], lw[2 * kLSegs];  // ... the leader's area interval a +- w
+    int any;                      // some leader was beaten in this round
+};
+
+// A workgroup barrier that orders LDS accesses only: global stores still in
+// flight (counters, vertex records) need not complete first.
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// float -> unsigned with the same order
+__device__ __forceinline__ unsigned okey(float f)
+{
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ int lseg_of(const LTail& L, int S, int i)
+{
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.seg[mid].vs <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Runs passes `pass`, pass + 1, ... of table `cur` in LDS. Returns false
+// when the table outgrew the LDS first: it is then written back (points at
+// their slots in buffer `cur`, the table, the pass) for the passes kernel.
+__device__ __forceinline__ bool lds_passes(const HullArgs& a, int cur, int pass, LTail& L, Pair* red,
+                                           Counters& ctr)
+{
+    const int t = (int)threadIdx.x;
+    const bool f64 = a.fp64 != 0;
+    int2* vl = (a.vcap > 0 && a.G == 1) ? a.vlist : nullptr;
+    int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
+    // the vertex list's length and the stamp count are this workgroup's
+    // alone from here: kept locally, so that a pass waits on no global read
+    int vcount = ld_flag(&a.info->vcount);
+    int nst = ld_flag(&a.info->nstamps);
+    for (int u = t; u < S; u += kBlock) {
+        const Seg g = gld(a.segs[cur] + u);
+        LSeg q;
+        q.ax = g.ax; q.ay = g.ay; q.bx = g.bx; q.by = g.by; q.cx = g.cx; q.cy = g.cy;
+        q.off = g.off; q.len = g.len;
+        q.cid = gld(a.seg_cid[cur] + u);
+        q.vs = gld(a.vstart[cur] + u);
+        L.seg[u] = q;
+    }
+    if (t == 0) L.seg[S].vs = V;
+    lds_sync();
+    for (int i = t; i < V; i += kBlock) {
+        const LSeg& q = L.seg[lseg_of(L, S, i)];
+        const int p = q.off + (i - q.vs);
+        L.x[i] = gld(a.X[cur] + p);
+        L.y[i] = gld(a.Y[cur] + p);
+        L.id[i] = gld(a.I[cur] + p);
+    }
+    lds_sync();
+    for (;; ++pass) {
+        note_pass(a, pass, S, V);
+        if (S <= 0) break;
+        if (pass >= kMaxInfoPasses || (S > kLSegs / 2 && V > kLSegs)) {
+            // hand the table back to the passes kernel
+            for (int i = t; i < V; i += kBlock) {
+                const LSeg& q = L.seg[lseg_of(L, S, i)];
+                const int p = q.off + (i - q.vs);
+                gst(a.X[cur] + p, L.x[i]);
+                gst(a.Y[cur] + p, L.y[i]);
+                gst(a.I[cur] + p, L.id[i]);
+            }
+            for (int u = t; u < S; u += kBlock) {
+                const LSeg q = L.seg[u];
+                Seg g;
+                g.ax = q.ax; g.ay = q.ay; g.bx = q.bx; g.by = q.by; g.cx = q.cx; g.cy = q.cy;
+                g.off = q.off; g.len = q.len;
+                gst(a.segs[cur] + u, g);
+                a.seg_cid[cur][u] = q.cid;
+                a.vstart[cur][u] = q.vs;
+            }
+            if (t == 0) {
+                a.vstart[cur][S] = V;
+                a.sv[2 * cur] = S;
+                a.sv[2 * cur + 1] = V;
+                auto* ws = static_cast<StreamWs*>(a.sws);
+                ws->state[0] = cur;
+                ws->state[1] = pass;
+            }
+            return false;
+        }
+        for (int u = t; u < 2 * S; u += kBlock) {
+            L.cnt[u] = 0;
+            L.key[u] = 0u;
+            L.lead[u] = 0x7fffffff;
+        }
+        if (t == 0) L.any = 0;
+        lds_sync();
+        // 1. each point: its child, its rank there, its area interval
+        float pa[kLPer], pw[kLPer];
+        int pk[kLPer];  // segment << 14 | child << 13 | rank, or -1
+#pragma unroll
+        for (int r = 0; r < kLPer; ++r) {
+            const int i = t + kBlock * r;
+            pk[r] = -1;
+            pa[r] = 0.0f; pw[r] = 0.0f;
+            if (i < V) {
+                const int sg = lseg_of(L, S, i);
+                const LSeg& q = L.seg[sg];
+                const float x = L.x[i], y = L.y[i];
+                const Edge e0 = make_edge(q.ax, q.ay, q.cx, q.cy), e1 = make_edge(q.cx, q.cy, q.bx, q.by);
+                const Orient32 o1 = orient32(e0, x, y), o2 = orient32(e1, x, y);
+                int s1 = fast_sign(o1, f64), s2 = fast_sign(o2, f64);
+                settle(s1, s1 == 0, e0, x, y, ctr.orient_exact);
+                settle(s2, s1 >= 0 && s2 == 0, e1, x, y, ctr.orient_exact);
+                ctr.orient += 2;
+                const int k = s1 < 0 ? 0 : (s2 < 0 ? 1 : -1);
+                if (k >= 0) {
+                    pa[r] = -(k == 0 ? o1.d : o2.d);
+                    pw[r] = 2.0f * (k == 0 ? o1.es : o2.es);
+                    const int u = 2 * sg + k;
+                    const int rank = atomicAdd(&L.cnt[u], 1);
+                    atomicMax(&L.key[u], okey(pa[r] - pw[r]));
+                    pk[r] = (sg << 14) | (k << 13) | rank;
+                }
+            }
+        }
+        lds_sync();
+        // 2. the farthest point of each child. Candidates: points whose upper
+        // bound reaches the child's largest lower bound (every point in the
+        // float64-only mode); the first leader is the lowest position
+        // holding that lower bound.
+        bool cand[kLPer];
+#pragma unroll
+        for (int r = 0; r < kLPer; ++r) {
+            cand[r] = false;
+            if (pk[r] >= 0) {
+                const int u = pk[r] >> 13;
+                const unsigned kmax = L.key[u];
+                const unsigned lo = okey(pa[r] - pw[r]);
+                cand[r] = f64 || okey(pa[r] + pw[r]) >= kmax;
+                if (lo == kmax) atomicMin(&L.lead[u], t + kBlock * r);
+            }
+        }
+        lds_sync();
+#pragma unroll
+        for (int r = 0; r < kLPer; ++r) {
+            if (cand[r] && L.lead[pk[r] >> 13] == t + kBlock * r) {
+                L.la[pk[r] >> 13] = pa[r];
+                L.lw[pk[r] >> 13] = pw[r];
+            }
+        }
+        lds_sync();
+        for (;;) {
+            // every other candidate against the leader
+#pragma unroll
+            for (int r = 0; r < kLPer; ++r) {
+                if (!cand[r]) continue;
+                const int u = pk[r] >> 13, i = t + kBlock * r;
+                const int l = L.lead[u];
+                if (l == i) continue;
+                const LSeg& q = L.seg[pk[r] >> 14];
+                const Edge E = (u & 1) ? make_edge(q.cx, q.cy, q.bx, q.by) : make_edge(q.ax, q.ay, q.cx, q.cy);
+                Cand P, Q;
+                P.a = pa[r]; P.w = pw[r]; P.x = L.x[i]; P.y = L.y[i]; P.id = L.id[i];
+                Q.a = L.la[u]; Q.w = L.lw[u]; Q.x = L.x[l]; Q.y = L.y[l]; Q.id = L.id[l];
+                if (beats(E, P, Q, f64, ctr.cmp_exact)) {
+                    atomicOr(&L.cnt[u], (int)0x80000000u);
+                    L.any = 1;
+                } else {
+                    cand[r] = false;
+                }
+            }
+            lds_sync();
+            if (!L.any) break;  // (uniform)
+            // a beaten leader steps down; its challengers elect the lowest position
+#pragma unroll
+            for (int r = 0; r < kLPer; ++r)
+                if (cand[r] && L.cnt[pk[r] >> 13] < 0 && L.lead[pk[r] >> 13] == t + kBlock * r) cand[r] = false;
+            lds_sync();
+            for (int u = t; u < 2 * S; u += kBlock)
+                if (L.cnt[u] < 0) L.lead[u] = 0x7fffffff;
+            lds_sync();
+#pragma unroll
+            for (int r = 0; r < kLPer; ++r)
+                if (cand[r] && L.cnt[pk[r] >> 13] < 0) atomicMin(&L.lead[pk[r] >> 13], t + kBlock * r);
+            lds_sync();
+#pragma unroll
+            for (int r = 0; r < kLPer; ++r) {
+                if (cand[r] && L.cnt[pk[r] >> 13] < 0 && L.lead[pk[r] >> 13] == t + kBlock * r) {
+                    L.la[pk[r] >> 13] = pa[r];
+                    L.lw[pk[r] >> 13] = pw[r];
+                }
+            }
+            lds_sync();
+            for (int u = t; u < 2 * S; u += kBlock) L.cnt[u] &= 0x7fffffff;
+            if (t == 0) L.any = 0;
+            lds_sync();
+        }
+        // 3. the children of segment t, C's vertex key, the next table
+        LSeg mine = {};
+        int n0 = 0, n1 = 0;
+        LSeg ch0 = {}, ch1 = {};
+        if (t < S) {
+            mine = L.seg[t];
+            n0 = L.cnt[2 * t];
+            n1 = L.cnt[2 * t + 1];
+        }
+        Pair tot;
+        const Pair ex = block_excl_scan(Pair{n0 + n1, (n0 > 0) + (n1 > 0)}, red, &tot);
+        if (t < S) {
+            // C is a vertex: its key is the first slot after the (A, C) points
+            const int key = mine.off + n0;
+            atomicOr((unsigned long long*)&a.bitmap[key >> 6], 1ull << (key & 63));
+            gst(a.vidx + key, mine.cid);
+            if (vl && vcount + t < a.vcap) vl[vcount + t] = make_int2(key, mine.cid);
+            if (n0 > 0) {
+                const int l = L.lead[2 * t];
+                ch0.ax = mine.ax; ch0.ay = mine.ay; ch0.bx = mine.cx; ch0.by = mine.cy;
+                ch0.cx = L.x[l]; ch0.cy = L.y[l]; ch0.cid = L.id[l];
+                ch0.off = mine.off; ch0.len = n0; ch0.vs = ex.a;
+            }
+            if (n1 > 0) {
+                const int l = L.lead[2 * t + 1];
+                ch1.ax = mine.cx; ch1.ay = mine.cy; ch1.bx = mine.bx; ch1.by = mine.by;
+                ch1.cx = L.x[l]; ch1.cy = L.y[l]; ch1.cid = L.id[l];
+                ch1.off = mine.off + mine.len - n1; ch1.len = n1; ch1.vs = ex.a + n0;
+            }
+        }
+        lds_sync();  // every read of the table and of the leaders is done
+        if (t < S) {
+            int j = ex.b;
+            if (n0 > 0) L.seg[j++] = ch0;
+            if (n1 > 0) L.seg[j] = ch1;
+            L.key[2 * t] = (unsigned)ex.a;
+            L.key[2 * t + 1] = (unsigned)(ex.a + n0);
+        }
+        if (t == 0) L.seg[tot.b].vs = tot.a;
+        lds_sync();
+        // 4. every kept point to its child, in place: each thread reads its
+        // points, then (after the barrier) writes them
+        float px[kLPer], py[kLPer];
+        int pid[kLPer], dst[kLPer];
+#pragma unroll
+        for (int r = 0; r < kLPer; ++r) {
+            const int i = t + kBlock * r;
+            dst[r] = -1;
+            px[r] = 0.0f; py[r] = 0.0f; pid[r] = 0;
+            if (pk[r] >= 0) {
+                px[r] = L.x[i]; py[r] = L.y[i]; pid[r] = L.id[i];
+                dst[r] = (int)L.key[pk[r] >> 13] + (pk[r] & 0x1fff);
+            }
+        }
+        lds_sync();
+#pragma unroll
+        for (int r = 0; r < kLPer; ++r) {
+            if (dst[r] < 0) continue;
+            L.x[dst[r]] = px[r];
+            L.y[dst[r]] = py[r];
+            L.id[dst[r]] = pid[r];
+        }
+        lds_sync();
+        vcount += S;
+        if (t == 0) {
+            a.info->vcount = vcount;
+            if (a.timing && nst < kMaxStamps) {
+                a.info->stamp[nst] = wall_clock64();
+                a.info->stamp_tag[nst] = 100 + pass;
+                a.info->nstamps = ++nst;
+            }
+        }
+        S = tot.b;
+        V = tot.a;
+    }
+    if (t == 0) {
+        a.sv[2 * cur] = 0;
+        a.sv[2 * cur + 1] = 0;
+        auto* ws = static_cast<StreamWs*>(a.sws);
+        ws->state[0] = cur;
+        ws->state[1] = pass;
+    }
+    return true;
+}
+
 // The streaming path's last kernel (one workgroup, an ordinary launch): once
 // at most kTinyPoints points are left, the remaining passes in LDS (the
 // passes kernel's own tail) and the ordered emission of the vertex list.
@@ -1684,25 +2004,27 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
 // kernel continues from the state left in the workspace.
 __global__ __launch_bounds__(kBlock) void k_stail(HullArgs a)
 {
-    __shared__ uint4 lds[(sizeof(TinyLds) > sizeof(int2) * kSmallHull ? sizeof(TinyLds) : sizeof(int2) * kSmallHull) /
-                             16 + 1];
+    static_assert(sizeof(LTail) >= sizeof(int2) * kSmallHull, "the emission reuses the passes' LDS");
+    __shared__ LTail lds;
     __shared__ Pair red[kWaves];
     auto* ws = static_cast<StreamWs*>(a.sws);
     Counters ctr = {0u, 0u, 0u};
     if (ld_flag(a.err)) return;
     const int cur = ld_flag(&ws->state[0]) & 1, pass = ld_flag(&ws->state[1]);
     const int S = ld_flag(a.sv + 2 * cur), V = ld_flag(a.sv + 2 * cur + 1);
-    if (S > 0 && (V > kTinyPoints || pass >= kMaxInfoPasses)) return;  // left to the passes kernel
+    // left to the passes kernel: too many points, or a table that could outgrow the LDS
+    if (S > 0 && (V > kLPoints || (S > kLSegs / 2 && V > kLSegs) || pass >= kMaxInfoPasses)) return;
     if (S > 0) {
-        tiny_passes(a, cur, pass, *reinterpret_cast<TinyLds*>(lds), red, ctr);
+        const bool done = lds_passes(a, cur, pass, lds, red, ctr);
         flush_counters(a.stats, ctr);
+        if (!done) return;
     } else if (threadIdx.x == 0) {
         note_pass(a, pass, 0, 0);
     }
     __syncthreads();
     const int h = ld_flag(&a.info->vcount);
     if (!(h <= kSmallHull && h <= a.vcap)) return;  // the grid emission in the passes kernel
-    emit_small(a, h, reinterpret_cast<int2*>(lds));
+    emit_small(a, h, reinterpret_cast<int2*>(&lds));
     if (threadIdx.x == 0) {
         a.info->stream_done = 1;
         stamp(a, 4);

@@ -103,9 +103,9 @@ def launch_bytes(launches: list, st: dict, n: int) -> list:
         elif name == "k_sfirst<semistatic>":
             b = 0 if line else 8 * n + 12 * int(st["first_survivors"])
         elif name == "k_spass":
-            # a streaming pass runs while the table qualifies: >= 1024 points
-            # in at most 256 segments
-            if k_spass < len(pts) and k_spass == spass_ran and pts[k_spass] > 1024 and \
+            # a streaming pass runs while the table qualifies: more than 6144
+            # points (fewer: the LDS passes) in at most 256 segments
+            if k_spass < len(pts) and k_spass == spass_ran and pts[k_spass] > 6144 and \
                     int(st["pass_segments"][k_spass]) <= 256:
                 b = pass_b(k_spass)
                 spass_ran += 1
@@ -603,6 +603,9 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32-semistatic", "fp64"],
                     help="fp32: float32 filters with exact fallback (the static line filter where it "
                          "applies); fp32-semistatic: without the line filter; fp64: every predicate exact")
+    ap.add_argument("--no-streaming", action="store_true",
+                    help="run the general path (the persistent cooperative kernel) instead of the streaming "
+                         "kernels of a large single hull")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=2000, help="serving requests after 200 warm-up (0: skip)")
     ap.add_argument("--no-breakdown", action="store_true",
@@ -650,6 +653,8 @@ def main() -> int:
     H = sqh.Hull(0)
     H.set_precision({"fp32": sqh.SQH_FP32_FILTER, "fp32-semistatic": sqh.SQH_FP32_SEMISTATIC,
                      "fp64": sqh.SQH_FP64_ONLY}[args.precision])
+    if args.no_streaming:
+        H.set_streaming(False)
     out = torch.empty(max(args.n, 1), dtype=torch.int32, device=dev)
     H.workspace(args.n, 1)
 
@@ -683,7 +688,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"single hull, {args.kind}, n={args.n}, float32, seed {args.seed}",
                    "n": args.n, "kind": args.kind, "seed": args.seed,
-                   "precision": args.precision},
+                   "precision": args.precision, "streaming": not args.no_streaming},
         "roofline": {
             "bound": "hbm",
             "kernel": dom,

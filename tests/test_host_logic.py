@@ -31,15 +31,15 @@ def test_call_bytes_model():
 def test_launch_bytes_model():
     # streaming path: seed and split read the input, the line-filter first
     # compaction reads it and writes the survivors (the other mode's kernel
-    # returns at once), k_spass launches take the passes over more than 1024
+    # returns at once), k_spass launches take the passes over more than 6144
     # points in at most 256 segments in order, the passes kernel the rest
     n = 1_000_000
-    st = {"pass_points": [400000, 90000, 3000, 500, 20], "pass_segments": [4, 8, 300, 20, 4], "passes": 5,
+    st = {"pass_points": [400000, 90000, 9000, 500, 20], "pass_segments": [4, 8, 300, 20, 4], "passes": 5,
           "first_survivors": 400000, "line_filter": 1}
     names = ["k_reset", "k_sseed", "k_ssplit", "k_sfirst<line>", "k_sfirst<semistatic>",
              "k_spass", "k_spass", "k_spass", "k_stail", "k_hull<passes>"]
     b = bench.launch_bytes([(x, 0.0) for x in names], st, n)
-    p = [12 * (400000 + 90000), 12 * (90000 + 3000), 12 * (3000 + 500), 12 * (500 + 20), 12 * 20]
+    p = [12 * (400000 + 90000), 12 * (90000 + 9000), 12 * (9000 + 500), 12 * (500 + 20), 12 * 20]
     assert b == [0, 8 * n, 8 * n, 8 * n + 12 * 400000, 0, p[0], p[1], 0, 0, p[2] + p[3] + p[4]]
     st["line_filter"] = 0
     b = bench.launch_bytes([(x, 0.0) for x in names], st, n)
@@ -48,7 +48,7 @@ def test_launch_bytes_model():
     assert sum(b) == bench.call_bytes(st, n)
     # no passes kernel: the tail takes the rest
     st["pass_segments"] = [4, 8, 20, 20, 4]
-    st["pass_points"] = [400000, 90000, 3000, 500, 20]
+    st["pass_points"] = [400000, 90000, 9000, 500, 20]
     b = bench.launch_bytes([(x, 0.0) for x in names[:-1]], st, n)
     assert b[5:8] == [p[0], p[1], p[2]] and b[8] == p[3] + p[4]
     assert sum(b) == bench.call_bytes(st, n)

@@ -48,6 +48,24 @@ constexpr int kStatSlots = 64;
 enum { kModeAgg = 0, kModeScatter = 1 };
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Wave-wide inclusive prefix sum with DPP moves (every lane active): adds
+// within each 16-lane row from 1, 2, 4 and 8 lanes back (lanes with no
+// source add 0), then row 0's total into row 1 and row 2's into row 3
+// (row_bcast:15), then the total of rows 0-1 into rows 2 and 3
+// (row_bcast:31). Lane 63 ends with the wave's total.
+__device__ __forceinline__ int wave_incl_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+// The wave's total, in every lane (scalar).
+__device__ __forceinline__ int wave_total(int v) { return __builtin_amdgcn_readlane(wave_incl_sum(v), 63); }
 __device__ __forceinline__ uint64_t mask_lt(int l) { return (1ull << l) - 1ull; }
 __device__ __forceinline__ uint64_t mask_le(int l) { return l >= 63 ? ~0ull : ((2ull << l) - 1ull); }
 // bits [lo, hi], 0 <= lo, hi <= 63; empty if hi < lo
@@ -172,9 +190,7 @@ __device__ __forceinline__ void flush_counters(uint32_t* stats, Counters& ctr)
     const uint32_t v[3] = {ctr.orient, ctr.orient_exact, ctr.cmp_exact};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        uint32_t s = v[i];
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m);
+        const uint32_t s = (uint32_t)wave_total((int)v[i]);
         if (lane_id() == 0 && s) atomicAdd(&stats[(blockIdx.x % kStatSlots) * 4 + i], s);
     }
     ctr.orient = ctr.orient_exact = ctr.cmp_exact = 0;

@@ -650,8 +650,9 @@ struct PolPass {
 // before arriving and one acquire fence after leaving, and spins with
 // relaxed loads. The last arriver of a sub-counter acquires (so later
 // arrivals carry the earlier ones' writes) before arriving at the top
-// counter; the last top arriver publishes the new generation with a release
-// store. Bounded spin: on timeout the error flag is raised and the
+// counter with a release (which also orders its reset of the sub-counter
+// before the next generation); the last top arriver publishes the new
+// generation with a release store. Bounded spin: on timeout the error flag is raised and the
 // workgroup continues.
 constexpr int kBarSub = 16;
 struct GridBar {
@@ -688,7 +689,9 @@ __device__ __forceinline__ void grid_sync(GridBar* bar, int* err)
         if (a == nsub - 1) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(&bar->sub[i][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned int t = __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // release: the reset happens before the last top arriver's
+            // acquire, hence before the new generation and the next arrivals
+            const unsigned int t = __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (t == ntop - 1) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(&bar->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -718,12 +721,7 @@ struct Pair {
 __device__ __forceinline__ Pair block_excl_scan(Pair v, Pair* red, Pair* tot)
 {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
-    Pair inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int oa = __shfl_up(inc.a, d), ob = __shfl_up(inc.b, d);
-        if (lane >= d) { inc.a += oa; inc.b += ob; }
-    }
+    const Pair inc = {wave_incl_sum(v.a), wave_incl_sum(v.b)};
     __syncthreads();
     if (lane == 63) red[w] = inc;
     __syncthreads();

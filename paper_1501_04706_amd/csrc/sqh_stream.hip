@@ -375,12 +375,7 @@ __device__ __forceinline__ int lanes_below(uint64_t M)
 __device__ __forceinline__ Pair sblock_excl_scan(Pair v, Pair* red, Pair* tot)
 {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
-    Pair inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int oa = __shfl_up(inc.a, d), ob = __shfl_up(inc.b, d);
-        if (lane >= d) { inc.a += oa; inc.b += ob; }
-    }
+    const Pair inc = {wave_incl_sum(v.a), wave_incl_sum(v.b)};
     __syncthreads();
     if (lane == 63) red[w] = inc;
     __syncthreads();
@@ -394,12 +389,7 @@ __device__ __forceinline__ Pair sblock_excl_scan(Pair v, Pair* red, Pair* tot)
     return Pair{off.a + inc.a - v.a, off.b + inc.b - v.b};
 }
 
-__device__ __forceinline__ int wave_sum(int v)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-    return v;
-}
+__device__ __forceinline__ int wave_sum(int v) { return wave_total(v); }
 
 // Lower side (strictly right of A->B): edges A->C_lo (bucket 0) and C_lo->B
 // (bucket 1); upper side: B->C_up (2) and C_up->A (3). Section 4.4.3 keeps

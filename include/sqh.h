@@ -130,7 +130,7 @@ int sqh_set_precision(sqh_ctx *ctx, int mode);
 
 /*
  * Streaming path on (on != 0, the default) or off. On, a call on one set of
- * at least 2^20 points (no pre-filter, partition variant, 16-byte aligned
+ * at least 2^16 points (no pre-filter, partition variant, 16-byte aligned
  * input) runs its first phases and passes over few large segments as
  * ordinary launches that never wait for one another, and the cooperative
  * passes kernel only for what they leave. The output is identical either

@@ -40,7 +40,7 @@ constexpr int kMaxSGrid = 1024;               // workgroups of a streaming launc
 constexpr int kSRows = 8;                     // rows of point pairs per wave and tile
 constexpr int kSTilePairs = kSBlock * kSRows;  // pairs per workgroup tile
 constexpr int kSTile = 2 * kSTilePairs;       // points per workgroup tile (16384)
-constexpr int kStreamMin = 1 << 20;           // single hulls of at least this many points take this path
+constexpr int kStreamMin = 1 << 16;           // single hulls of at least this many points take this path
 
 // Farthest-point candidate of one lane: the area interval [lo, hi] =
 // [fl(a - w), fl(a + w)] of the float32 estimate a with error bound w, and

@@ -1,6 +1,6 @@
 """GPU parity of the streaming path (large single hulls) against the oracle.
 
-Calls on one set of at least 2^20 points run the first phases and the passes
+Calls on one set of at least 2^16 points run the first phases and the passes
 over few large segments as ordinary launches; these cases check that path
 against the oracle and against the general path, at the size threshold and
 with a ragged tail, in every precision mode, with and without the static line
@@ -17,7 +17,8 @@ from paper_1501_04706_amd import sqh, workloads
 
 pytestmark = pytest.mark.gpu
 
-THRESHOLD = 1 << 20
+THRESHOLD = 1 << 16
+LARGE = 1 << 20  # several streaming passes before the LDS passes
 
 
 def say(msg):
@@ -46,7 +47,7 @@ def run(H, xy, streaming=True, precision=sqh.SQH_FP32_FILTER):
         H.set_precision(sqh.SQH_FP32_FILTER)
 
 
-@pytest.mark.parametrize("n", [THRESHOLD, THRESHOLD + 12345])
+@pytest.mark.parametrize("n", [THRESHOLD, THRESHOLD + 12345, LARGE, LARGE + 12345])
 @pytest.mark.parametrize("kind", ["square", "disk", "circle", "grid"])
 def test_stream_matches_general(H, kind, n):
     say(f"stream vs general: {kind} n={n}")
@@ -61,7 +62,7 @@ def test_stream_matches_general(H, kind, n):
 
 
 def test_below_threshold_takes_general_path(H):
-    say("n = 2^20 - 1")
+    say("n = 2^16 - 1")
     xy = workloads.square(THRESHOLD - 1, 12)
     got, st = run(H, xy)
     assert st["stream_path"] == 0
@@ -92,7 +93,7 @@ def test_stream_line_filter_domain(H, case):
     # margin (coordinates near 2^-90, kept normal), and a thin strip that
     # keeps it
     say(f"line filter domain: {case}")
-    xy = workloads.disk(THRESHOLD + 77, 14).astype(np.float64)
+    xy = workloads.disk(LARGE + 77, 14).astype(np.float64)
     if case == "offset":
         xy += 4096.0
     elif case == "huge":
@@ -120,7 +121,7 @@ def test_stream_hands_over_to_passes_kernel(H):
 
 
 def test_stream_degenerate(H):
-    n = THRESHOLD + 5
+    n = LARGE + 5
     cases = {
         "one position": np.full((n, 2), 0.25, np.float32),
         "two positions": np.where((np.arange(n) % 3 == 0)[:, None], [1.0, 2.0], [-3.0, 0.5]).astype(np.float32),
@@ -139,8 +140,8 @@ def test_stream_degenerate(H):
 def test_unaligned_input_takes_general_path(H):
     import torch
     say("input at an 8-byte offset")
-    xy = workloads.square(THRESHOLD + 1, 17)
-    big = torch.zeros((THRESHOLD + 2, 2), dtype=torch.float32, device="cuda")
+    xy = workloads.square(LARGE + 1, 17)
+    big = torch.zeros((LARGE + 2, 2), dtype=torch.float32, device="cuda")
     big[1:] = torch.from_numpy(xy).to("cuda")
     view = big[1:]
     assert view.data_ptr() % 16 == 8
@@ -155,7 +156,7 @@ def test_stream_ignores_memory_past_the_end(H, mode, off):
     # the input sits at the start of a larger buffer whose tail holds points
     # far outside its hull: a ragged last tile must never take them in
     import torch
-    n = THRESHOLD + 77
+    n = LARGE + 77
     say(f"memory past the end: mode {mode} offset {off}")
     xy = (workloads.disk(n, 18).astype(np.float64) + off).astype(np.float32)
     big = torch.full((n + 16384, 2), off + 1000.0, dtype=torch.float32, device="cuda")
@@ -174,7 +175,7 @@ def test_stream_pass_count_adapts(H):
     # a context enqueues as many streaming passes as the last call of the
     # size class needed (plus one on few workgroups); a call that needs more
     # is finished by the passes kernel, and the next one gets them all
-    n = THRESHOLD + 3
+    n = LARGE + 3
     sq = workloads.square(n, 19)
     dk = workloads.disk(n, 19)
     want_sq = [int(v) for v in oracle.c_hull(sq)]

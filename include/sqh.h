@@ -419,6 +419,42 @@ int sqh_get_launch_times(const sqh_ctx *ctx, const char **names, double *ms, int
  * number copied (0 when tracing is off), or SQH_EINVAL. */
 int sqh_get_trace(const sqh_ctx *ctx, uint64_t *out, int max_entries);
 
+/*
+ * Test hooks (they run the device code of the hull path on caller-given
+ * cases; no hull call uses them). Device pointers; each call synchronises
+ * `stream` and returns SQH_OK, SQH_EINVAL (bad size or null pointer) or
+ * SQH_EDEVICE.
+ *
+ * sqh_diag_orient: for each of n cases of 6 floats (ox, oy, ex, ey, px, py),
+ * d_sign[i] = the sign of orient(o, e, p) = (ex-ox)(py-oy) - (ey-oy)(px-ox)
+ * as the kernels decide it (float32 semi-static filter, then the exact
+ * path; every test exact if fp64_only), d_flags[i] bit 0 = the filter
+ * decided, and d_vals[4i..4i+3] = d, es (the filter's value and bound:
+ * certified when |d| > es, |d - orient| <= 2 es) and t, m (the static line
+ * filter of section 4.4.3's edge tests with Mx, My taken from the case's
+ * own coordinates: |t - orient| < m; m = -1 where it does not apply).
+ */
+int sqh_diag_orient(const float *d_tri, int64_t n, int fp64_only, int32_t *d_sign, float *d_vals, int32_t *d_flags,
+                    void *stream);
+
+/*
+ * sqh_diag_compare: for each of n cases of 8 floats (ox, oy, ex, ey, px, py,
+ * qx, qy) with indices d_ids[2i], d_ids[2i+1], d_out[i] bit 0 = P comes
+ * before Q in the farthest-point order for edge o -> e (section 4.4.1:
+ * larger area right of the edge; equal areas: earlier along the edge; the
+ * same position: lower index), bit 1 = Q before P, both as the kernels
+ * decide from float32 intervals and the exact path.
+ */
+int sqh_diag_compare(const float *d_cases, const int32_t *d_ids, int64_t n, int fp64_only, int32_t *d_out,
+                     void *stream);
+
+/*
+ * sqh_diag_scan: the workgroup scan of the kernels (section 2's scan over
+ * 1024-value runs): d_ex_a[i] = sum of d_in over the run before i, d_ex_b[i]
+ * = i's position in its run, d_tot[2r], d_tot[2r+1] = run r's totals.
+ */
+int sqh_diag_scan(const int32_t *d_in, int64_t n, int32_t *d_ex_a, int32_t *d_ex_b, int32_t *d_tot, void *stream);
+
 /* Static description of a return code. */
 const char *sqh_strerror(int code);
 

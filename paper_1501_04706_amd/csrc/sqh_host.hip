@@ -18,6 +18,7 @@
 #include "sqh_kernels.hip"
 #include "sqh_stream.hip"
 #include "sqh_engine.hip"
+#include "sqh_diag.hip"
 
 using namespace sqh;
 
@@ -1406,6 +1407,51 @@ const char* sqh_strerror(int code)
     case SQH_ENOTFOUND: return "no finished request";
     default: return "unknown error";
     }
+}
+
+}  // extern "C"
+
+// ---- test hooks ----------------------------------------------------------
+
+namespace {
+int diag_finish(hipStream_t st)
+{
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    return SQH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sqh_diag_orient(const float* d_tri, int64_t n, int fp64_only, int32_t* d_sign, float* d_vals, int32_t* d_flags,
+                    void* stream)
+{
+    if (n < 0 || n > INT32_MAX / 6 || (n > 0 && (!d_tri || !d_sign || !d_vals || !d_flags))) return SQH_EINVAL;
+    if (n == 0) return SQH_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    k_diag_orient<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d_tri, (int)n, fp64_only != 0, d_sign, d_vals,
+                                                             d_flags);
+    return diag_finish(st);
+}
+
+int sqh_diag_compare(const float* d_cases, const int32_t* d_ids, int64_t n, int fp64_only, int32_t* d_out,
+                     void* stream)
+{
+    if (n < 0 || n > INT32_MAX / 8 || (n > 0 && (!d_cases || !d_ids || !d_out))) return SQH_EINVAL;
+    if (n == 0) return SQH_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    k_diag_compare<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d_cases, d_ids, (int)n, fp64_only != 0, d_out);
+    return diag_finish(st);
+}
+
+int sqh_diag_scan(const int32_t* d_in, int64_t n, int32_t* d_ex_a, int32_t* d_ex_b, int32_t* d_tot, void* stream)
+{
+    if (n < 0 || n > INT32_MAX - kBlock || (n > 0 && (!d_in || !d_ex_a || !d_ex_b || !d_tot))) return SQH_EINVAL;
+    if (n == 0) return SQH_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    k_diag_scan<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(d_in, (int)n, d_ex_a, d_ex_b, d_tot);
+    return diag_finish(st);
 }
 
 }  // extern "C"

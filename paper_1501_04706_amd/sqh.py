@@ -112,6 +112,12 @@ def load() -> ctypes.CDLL:
     lib.sqh_set_variant.restype = c_int
     lib.sqh_set_streaming.argtypes = [vp, c_int]
     lib.sqh_set_streaming.restype = c_int
+    lib.sqh_diag_orient.argtypes = [vp, i64, c_int, vp, vp, vp, vp]
+    lib.sqh_diag_orient.restype = c_int
+    lib.sqh_diag_compare.argtypes = [vp, vp, i64, c_int, vp, vp]
+    lib.sqh_diag_compare.restype = c_int
+    lib.sqh_diag_scan.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.sqh_diag_scan.restype = c_int
     lib.sqh_set_launch_timing.argtypes = [vp, c_int, ctypes.c_char_p]
     lib.sqh_set_launch_timing.restype = c_int
     lib.sqh_get_launch_times.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -208,6 +214,19 @@ def sqh_set_variant(ctx: int, variant: int) -> int:
 
 def sqh_set_streaming(ctx: int, on: int) -> int:
     return load().sqh_set_streaming(ctx, on)
+
+
+def sqh_diag_orient(tri, n: int, fp64_only: int, sign, vals, flags, stream=None) -> int:
+    return load().sqh_diag_orient(_ptr(tri), n, fp64_only, _ptr(sign), _ptr(vals), _ptr(flags),
+                                  _stream_handle(stream))
+
+
+def sqh_diag_compare(cases, ids, n: int, fp64_only: int, out, stream=None) -> int:
+    return load().sqh_diag_compare(_ptr(cases), _ptr(ids), n, fp64_only, _ptr(out), _stream_handle(stream))
+
+
+def sqh_diag_scan(x, n: int, ex_a, ex_b, tot, stream=None) -> int:
+    return load().sqh_diag_scan(_ptr(x), n, _ptr(ex_a), _ptr(ex_b), _ptr(tot), _stream_handle(stream))
 
 
 def sqh_set_launch_timing(ctx: int, on: int, only: str | None = None) -> int:

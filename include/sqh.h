@@ -195,6 +195,18 @@ int sqh_hull(sqh_ctx *ctx, const float *d_xy, int64_t n, int32_t *d_out, int64_t
              int64_t *h_count, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
+ * The same hull from separate coordinate arrays (structure of arrays):
+ * d_x[i], d_y[i] (device, float32, n each) are point i. One streaming kernel
+ * interleaves them into the front of the workspace (8 bytes per point,
+ * 16-byte aligned), then the call runs as sqh_hull on that copy, so indices,
+ * order, errors and synchronisation are those of sqh_hull. The workspace
+ * needs ws_bytes >= sqh_workspace_bytes_soa(n) (0 when n is out of range).
+ */
+size_t sqh_workspace_bytes_soa(int64_t n);
+int sqh_hull_soa(sqh_ctx *ctx, const float *d_x, const float *d_y, int64_t n, int32_t *d_out, int64_t out_cap,
+                 int64_t *h_count, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
  * sqh_hull without a caller workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation). The library keeps one static scratch

@@ -692,6 +692,16 @@ void eng_free(sqh_engine* e, int64_t base, int64_t alloc)
 
 }  // namespace
 
+// Structure-of-arrays input: the interleaved copy at the front of the
+// workspace (8 bytes per point, rounded up to the workspace alignment).
+inline size_t soa_copy_bytes(int64_t n) { return ((size_t)n * sizeof(float2) + kAlign - 1) / kAlign * kAlign; }
+
+__global__ __launch_bounds__(256) void k_interleave(const float* x, const float* y, float2* xy, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        xy[i] = make_float2(x[i], y[i]);
+}
+
 extern "C" {
 
 int sqh_create(sqh_ctx** out, int device)
@@ -803,6 +813,33 @@ int sqh_hull(sqh_ctx* c, const float* d_xy, int64_t n, int32_t* d_out, int64_t o
     *h_count = 0;
     return run(c, d_xy, n, 1, nullptr, d_out, nullptr, out_cap, h_count, d_ws, ws_bytes,
                static_cast<hipStream_t>(stream));
+}
+
+size_t sqh_workspace_bytes_soa(int64_t n)
+{
+    Layout L;
+    if (!make_layout(n, 1, L)) return 0;
+    return soa_copy_bytes(n) + L.bytes;
+}
+
+int sqh_hull_soa(sqh_ctx* c, const float* d_x, const float* d_y, int64_t n, int32_t* d_out, int64_t out_cap,
+                 int64_t* h_count, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (!c || !h_count || n < 0 || (n > 0 && (!d_x || !d_y))) return SQH_EINVAL;
+    *h_count = 0;
+    const size_t need = sqh_workspace_bytes_soa(n);
+    if (need == 0) return SQH_EINVAL;
+    if (!d_ws || ws_bytes < need) return SQH_ENOMEM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float2* xy = static_cast<float2*>(d_ws);
+    const size_t cb = soa_copy_bytes(n);
+    if (n > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+        k_interleave<<<grid, 256, 0, st>>>(d_x, d_y, xy, n);
+        HIP_OK(hipGetLastError());
+    }
+    return run(c, reinterpret_cast<const float*>(xy), n, 1, nullptr, d_out, nullptr, out_cap, h_count,
+               static_cast<unsigned char*>(d_ws) + cb, ws_bytes - cb, st);
 }
 
 int sqh_hull_noalloc(sqh_ctx* c, const float* d_xy, int64_t n, int32_t* d_out, int64_t out_cap, int64_t* h_count,

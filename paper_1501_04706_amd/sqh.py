@@ -112,6 +112,10 @@ def load() -> ctypes.CDLL:
     lib.sqh_set_variant.restype = c_int
     lib.sqh_set_streaming.argtypes = [vp, c_int]
     lib.sqh_set_streaming.restype = c_int
+    lib.sqh_workspace_bytes_soa.argtypes = [i64]
+    lib.sqh_workspace_bytes_soa.restype = ctypes.c_size_t
+    lib.sqh_hull_soa.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
+    lib.sqh_hull_soa.restype = c_int
     lib.sqh_diag_orient.argtypes = [vp, i64, c_int, vp, vp, vp, vp]
     lib.sqh_diag_orient.restype = c_int
     lib.sqh_diag_compare.argtypes = [vp, vp, i64, c_int, vp, vp]
@@ -214,6 +218,17 @@ def sqh_set_variant(ctx: int, variant: int) -> int:
 
 def sqh_set_streaming(ctx: int, on: int) -> int:
     return load().sqh_set_streaming(ctx, on)
+
+
+def sqh_workspace_bytes_soa(n: int) -> int:
+    return load().sqh_workspace_bytes_soa(n)
+
+
+def sqh_hull_soa(ctx: int, x, y, n: int, out, out_cap: int, ws, ws_bytes: int, stream=None):
+    h = ctypes.c_int64(0)
+    rc = load().sqh_hull_soa(ctx, _ptr(x), _ptr(y), n, _ptr(out), out_cap, ctypes.byref(h), _ptr(ws), ws_bytes,
+                             _stream_handle(stream))
+    return rc, h.value
 
 
 def sqh_diag_orient(tri, n: int, fp64_only: int, sign, vals, flags, stream=None) -> int:
@@ -466,6 +481,24 @@ class Hull:
         rc, h = sqh_hull(self.ctx, xy, n, out, out.numel(), ws, ws.numel(), stream)
         if rc != SQH_OK:
             raise SqhError(rc, "sqh_hull")
+        return out[:h]
+
+    def hull_soa(self, x, y, out=None, stream=None):
+        """x, y: (n,) float32 device tensors -> int32 device tensor of hull indices."""
+        torch = self.torch
+        x = x.contiguous()
+        y = y.contiguous()
+        n = x.shape[0]
+        need = sqh_workspace_bytes_soa(n)
+        if need == 0:
+            raise SqhError(SQH_EINVAL, "sqh_workspace_bytes_soa")
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        rc, h = sqh_hull_soa(self.ctx, x, y, n, out, out.numel(), self.ws, self.ws.numel(), stream)
+        if rc != SQH_OK:
+            raise SqhError(rc, "sqh_hull_soa")
         return out[:h]
 
     def hull_batched(self, xy, set_off, out=None, stream=None):

@@ -186,3 +186,32 @@ def test_stream_pass_count_adapts(H):
         assert got == want, i
         if i in (1, 3, 4):
             assert st["stream_path"] == 1, i
+
+
+@pytest.mark.parametrize("n", [0, 1, 5000, THRESHOLD + 99, LARGE + 77])
+def test_soa_input_matches_aos(H, n):
+    # separate x and y arrays give the same hull as the interleaved input
+    import torch
+    say(f"structure-of-arrays input n={n}")
+    xy = workloads.disk(n, 20)
+    x = torch.from_numpy(np.ascontiguousarray(xy[:, 0])).to("cuda")
+    y = torch.from_numpy(np.ascontiguousarray(xy[:, 1])).to("cuda")
+    got = [int(v) for v in H.hull_soa(x, y).cpu().numpy()]
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+    if n >= THRESHOLD:
+        assert H.stats()["stream_path"] in (1, 2)
+
+
+def test_soa_input_errors(H):
+    import torch
+    x = torch.zeros(10, dtype=torch.float32, device="cuda")
+    y = torch.zeros(10, dtype=torch.float32, device="cuda")
+    y[3] = float("nan")
+    with pytest.raises(sqh.SqhError) as e:
+        H.hull_soa(x, y)
+    assert e.value.code == sqh.SQH_EINVAL
+    ws = H.workspace(10, 1)
+    out = torch.empty(10, dtype=torch.int32, device="cuda")
+    rc, _ = sqh.sqh_hull_soa(H.ctx, x, x, 10, out, 10, ws, 16)
+    assert rc == sqh.SQH_ENOMEM
+    assert sqh.sqh_workspace_bytes_soa(-1) == 0

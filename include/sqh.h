@@ -250,7 +250,9 @@ int sqh_hull_batched(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, 
  * this problem's size class, floor(log2(n_total)). Candidates: the number of
  * workgroups of the persistent kernel (all co-resident ones, 3/4, 1/2, 1/4)
  * times the tail threshold (0, 2^13, 2^16 points; at most 256 segments) below which one
- * workgroup finishes the remaining passes. Later calls of any size use the
+ * workgroup finishes the remaining passes; for one set of at least 2^16
+ * points (streaming on) also the streaming path with 1024, 512 or 256
+ * workgroups per kernel. Later calls of any size use the
  * entry of the nearest class. The output of every shape is identical; only
  * time differs. Leaves the last candidate's result in d_out. Returns as
  * sqh_hull_batched, or SQH_ENOMEM when the context's table (40 classes) is
@@ -262,7 +264,9 @@ int sqh_autotune(sqh_ctx *ctx, const float *d_xy, const int64_t *d_set_off, int6
 
 /*
  * The context's tuning table as JSON,
- *   {"entries": [{"log2n": K, "grid": G, "tail": T}, ...], "engine_grid": E}
+ *   {"entries": [{"log2n": K, "grid": G, "tail": T, "stream": S, "sgrid": W}, ...], "engine_grid": E}
+ * (S = 1: large single hulls may take the streaming path; W = its kernels'
+ * workgroups, 0 = the default of twice the co-resident grid, at most 1024)
  * ("engine_grid", present when set, is the number of workgroups of a serving
  * engine step; by default a step leaves 1/8 of the compute units free so
  * that the copies of the next step's admissions can run beside it)
@@ -277,8 +281,9 @@ int sqh_get_tuning(const sqh_ctx *ctx, char *buf, size_t len);
  * of sqh_get_tuning; an empty list restores the built-in shape; a missing
  * "engine_grid" restores the engine default). Rejects the whole text with
  * SQH_EINVAL if an entry lacks a key or has grid outside [1, co-resident
- * workgroups of this device] or a negative tail, or engine_grid is outside
- * [1, co-resident workgroups].
+ * workgroups of this device], a negative tail, stream not 0 or 1, or sgrid
+ * outside [0, 1024], or engine_grid is outside [1, co-resident workgroups].
+ * "stream" and "sgrid" are optional (defaults 1 and 0).
  */
 int sqh_set_tuning(sqh_ctx *ctx, const char *json);
 

@@ -137,9 +137,11 @@ void scratch_init(int device)
 }
 
 struct TuneEntry {
-    int log2n;  // problem class: floor(log2(max(n_total, 1)))
-    int grid;   // workgroups of the persistent kernel
-    int tail;   // tail threshold (points) below which workgroup 0 finishes alone
+    int log2n;       // problem class: floor(log2(max(n_total, 1)))
+    int grid;        // workgroups of the persistent kernel
+    int tail;        // tail threshold (points) below which workgroup 0 finishes alone
+    int stream = 1;  // 1: large single hulls take the streaming path; 0: the persistent kernel
+    int sgrid = 0;   // workgroups of the streaming kernels (0: twice the co-resident grid, at most kMaxSGrid)
 };
 
 struct sqh_ctx {
@@ -208,6 +210,8 @@ TuneEntry pick_tuning(const sqh_ctx* ctx, int64_t n_total)
             best = d;
             t.grid = ctx->tune[i].grid;
             t.tail = ctx->tune[i].tail;
+            t.stream = ctx->tune[i].stream;
+            t.sgrid = ctx->tune[i].sgrid;
         }
     }
     t.grid = std::max(1, std::min(t.grid, ctx->max_grid));
@@ -277,7 +281,7 @@ int setup(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const int64
     a.sws = at(L.sws);
     a.sdone = N >= kStreamMin ? static_cast<StreamWs*>(a.sws)->done : nullptr;
     // one large set in plain mode, 16-byte aligned input: the streaming path
-    a.stream = (ctx->stream && nsets == 1 && N >= kStreamMin && !a.prefilter && !a.sorted &&
+    a.stream = (ctx->stream && tu.stream && nsets == 1 && N >= kStreamMin && !a.prefilter && !a.sorted &&
                 (reinterpret_cast<uintptr_t>(d_xy) & 15u) == 0)
                    ? 1
                    : 0;
@@ -338,11 +342,12 @@ inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fall
     }
     return n;
 }
-inline dim3 launch_grid(const Launch& l, int grid)
+inline dim3 launch_grid(const Launch& l, int grid, int sgrid)
 {
     if (l.f == reinterpret_cast<const void*>(k_stail)) return dim3(1);
     if (l.light) return dim3(kLightGrid);
-    return dim3(l.coop ? grid : std::min(2 * grid, kMaxSGrid));
+    if (l.coop) return dim3(grid);
+    return dim3(sgrid > 0 ? std::min(sgrid, kMaxSGrid) : std::min(2 * grid, kMaxSGrid));
 }
 inline dim3 launch_block(const Launch& l)
 {
@@ -390,7 +395,7 @@ inline int time_close(sqh_ctx* ctx, const char* name, hipStream_t st)
 }
 
 // Enqueue the workspace reset and the launches, bracketed by events.
-int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st, bool fallback = true)
+int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, int sgrid, hipStream_t st, bool fallback = true)
 {
     ctx->nl = 0;
     HIP_OK(hipEventRecord(ctx->ev0, st));
@@ -404,8 +409,9 @@ int enqueue(sqh_ctx* ctx, HullArgs& a, int reset_grid, int grid, hipStream_t st,
     const int nf = call_launches(a, L, fallback);
     for (int i = 0; i < nf; ++i) {
         if (time_open(ctx, kernel_name(L[i].f), st) != SQH_OK) return SQH_EDEVICE;
-        if (L[i].coop) HIP_OK(hipLaunchCooperativeKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
-        else HIP_OK(hipLaunchKernel(L[i].f, launch_grid(L[i], grid), launch_block(L[i]), argv, 0, st));
+        const dim3 gd = launch_grid(L[i], grid, sgrid);
+        if (L[i].coop) HIP_OK(hipLaunchCooperativeKernel(L[i].f, gd, launch_block(L[i]), argv, 0, st));
+        else HIP_OK(hipLaunchKernel(L[i].f, gd, launch_block(L[i]), argv, 0, st));
         if (time_close(ctx, kernel_name(L[i].f), st) != SQH_OK) return SQH_EDEVICE;
     }
     HIP_OK(hipEventRecord(ctx->ev1, st));
@@ -495,14 +501,14 @@ int run_tuned(sqh_ctx* ctx, const float* d_xy, int64_t N, int64_t nsets, const i
     int rc = setup(ctx, d_xy, N, nsets, d_set_off, d_out, d_out_off, out_cap, d_ws, ws_bytes, tu, a, reset_grid);
     if (rc != SQH_OK) return rc;
     if (!a.stream) {
-        rc = enqueue(ctx, a, reset_grid, tu.grid, st);
+        rc = enqueue(ctx, a, reset_grid, tu.grid, tu.sgrid, st);
         if (rc != SQH_OK) return rc;
         return collect(ctx, a, N, out_cap, h_total, st, true);
     }
     // streaming path: the passes kernel only if the streaming kernels left work
     const int cls = std::min(log2_class(N), 63);
     a.spasses = ctx->spass_used[cls] < 0 ? kStreamPassLaunches : ctx->spass_used[cls];
-    rc = enqueue(ctx, a, reset_grid, tu.grid, st, false);
+    rc = enqueue(ctx, a, reset_grid, tu.grid, tu.sgrid, st, false);
     if (rc != SQH_OK) return rc;
     rc = collect(ctx, a, N, out_cap, h_total, st, true);
     const HullInfo& hi = *ctx->hinfo;
@@ -878,29 +884,44 @@ int sqh_autotune(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, int64_
     const int m = c->max_grid;
     const int grids[4] = {m, std::max(1, (3 * m) / 4), std::max(1, m / 2), std::max(1, m / 4)};
     const int tails[3] = {0, 1 << 13, 1 << 16};
-    TuneEntry best{cls, m, kTailPoints};
-    double best_ms = 1e300;
-    int64_t h = 0;
+    // candidates: the persistent kernel at every grid x tail; for one large
+    // set also the streaming path at 1024, 512 and 256 workgroups
+    TuneEntry cand[16];
+    int nc = 0;
     for (int gi = 0; gi < 4; ++gi) {
         if (gi > 0 && grids[gi] == grids[gi - 1]) continue;
         for (int ti = 0; ti < 3; ++ti) {
-            const TuneEntry tu{cls, grids[gi], tails[ti]};
-            int rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes,
-                               st, tu);  // warm-up
+            cand[nc] = TuneEntry{cls, grids[gi], tails[ti]};
+            cand[nc++].stream = 0;
+        }
+    }
+    if (n_sets == 1 && n_total >= kStreamMin && c->stream) {
+        for (const int sg : {kMaxSGrid, kMaxSGrid / 2, kMaxSGrid / 4}) {
+            cand[nc] = TuneEntry{cls, m, kTailPoints};
+            cand[nc].stream = 1;
+            cand[nc++].sgrid = sg;
+        }
+    }
+    TuneEntry best{cls, m, kTailPoints};
+    double best_ms = 1e300;
+    int64_t h = 0;
+    for (int ci = 0; ci < nc; ++ci) {
+        const TuneEntry& tu = cand[ci];
+        int rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes, st,
+                           tu);  // warm-up
+        if (rc != SQH_OK) return rc;
+        double t[100];
+        for (int r = 0; r < reps; ++r) {
+            rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes, st,
+                           tu);
             if (rc != SQH_OK) return rc;
-            double t[100];
-            for (int r = 0; r < reps; ++r) {
-                rc = run_tuned(c, d_xy, n_total, n_sets, d_set_off, d_out, d_out_off, out_cap, &h, d_ws, ws_bytes,
-                               st, tu);
-                if (rc != SQH_OK) return rc;
-                t[r] = c->stats.ms_total;
-            }
-            std::sort(t, t + reps);
-            const double med = t[reps / 2];
-            if (med < best_ms) {
-                best_ms = med;
-                best = tu;
-            }
+            t[r] = c->stats.ms_total;
+        }
+        std::sort(t, t + reps);
+        const double med = t[reps / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = tu;
         }
     }
     int slot = -1;
@@ -917,11 +938,13 @@ int sqh_autotune(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, int64_
 int sqh_get_tuning(const sqh_ctx* c, char* buf, size_t len)
 {
     if (!c) return SQH_EINVAL;
-    char tmp[64 * sqh_ctx::kMaxTune + 64];
+    char tmp[96 * sqh_ctx::kMaxTune + 64];
     int n = snprintf(tmp, sizeof tmp, "{\"entries\": [");
     for (int i = 0; i < c->ntune; ++i)
-        n += snprintf(tmp + n, sizeof tmp - n, "%s{\"log2n\": %d, \"grid\": %d, \"tail\": %d}", i ? ", " : "",
-                      c->tune[i].log2n, c->tune[i].grid, c->tune[i].tail);
+        n += snprintf(tmp + n, sizeof tmp - n,
+                      "%s{\"log2n\": %d, \"grid\": %d, \"tail\": %d, \"stream\": %d, \"sgrid\": %d}",
+                      i ? ", " : "", c->tune[i].log2n, c->tune[i].grid, c->tune[i].tail, c->tune[i].stream,
+                      c->tune[i].sgrid);
     n += snprintf(tmp + n, sizeof tmp - n, "]");
     if (c->engine_grid > 0) n += snprintf(tmp + n, sizeof tmp - n, ", \"engine_grid\": %d", c->engine_grid);
     n += snprintf(tmp + n, sizeof tmp - n, "}");
@@ -947,12 +970,17 @@ int sqh_set_tuning(sqh_ctx* c, const char* json)
     for (const char* o = strchr(p, '{'); o && o < close; o = strchr(o + 1, '{')) {
         const char* e = strchr(o, '}');
         if (!e || e > close) return SQH_EINVAL;
-        long k = 0, g = 0, tl = 0;
+        long k = 0, g = 0, tl = 0, sm = 1, sg = 0;
         if (!read_int_key(o, e, "log2n", k) || !read_int_key(o, e, "grid", g) || !read_int_key(o, e, "tail", tl))
             return SQH_EINVAL;
+        (void)read_int_key(o, e, "stream", sm);  // optional keys
+        (void)read_int_key(o, e, "sgrid", sg);
         if (k < 0 || k > 62 || g < 1 || g > c->max_grid || tl < 0 || tl > INT32_MAX) return SQH_EINVAL;
+        if ((sm != 0 && sm != 1) || sg < 0 || sg > kMaxSGrid) return SQH_EINVAL;
         if (nt >= sqh_ctx::kMaxTune) return SQH_EINVAL;
-        t[nt++] = TuneEntry{(int)k, (int)g, (int)tl};
+        t[nt] = TuneEntry{(int)k, (int)g, (int)tl};
+        t[nt].stream = (int)sm;
+        t[nt++].sgrid = (int)sg;
     }
     long eg = 0;
     const char* after = close + 1;
@@ -1006,7 +1034,7 @@ int sqh_graph_create(sqh_ctx* c, const float* d_xy, const int64_t* d_set_off, in
     for (int i = 0; ok && i < nf; ++i) {
         hipKernelNodeParams hp = kp;
         hp.func = const_cast<void*>(L[i].f);
-        hp.gridDim = launch_grid(L[i], tu.grid);
+        hp.gridDim = launch_grid(L[i], tu.grid, tu.sgrid);
         hp.blockDim = launch_block(L[i]);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, g->graph, &prev, 1, &hp) == hipSuccess &&

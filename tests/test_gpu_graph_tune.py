@@ -59,7 +59,8 @@ def test_launch_shapes_same_hull(H, grid_frac, tail):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     grid = max(1, int(cus * grid_frac))
     say(f"launch shape grid={grid} tail={tail}")
-    H.set_tuning('{"entries": [{"log2n": 20, "grid": %d, "tail": %d}]}' % (grid, tail))
+    # "stream": 0 keeps the single hulls on the persistent kernel, whose shape this sets
+    H.set_tuning('{"entries": [{"log2n": 20, "grid": %d, "tail": %d, "stream": 0}]}' % (grid, tail))
     for kind, n in (("square", 1_000_000), ("circle", 200_000), ("grid", 300_000), ("disk", 5000)):
         xy = workloads.make(kind, n, 11)
         got = [int(v) for v in H.hull(torch.from_numpy(xy).cuda()).cpu().numpy()]
@@ -74,7 +75,9 @@ def test_tuning_text_rejected(H):
     say("tuning text validation")
     for bad in ['', '{}', '{"entries": [{"log2n": 3}]}', '{"entries": [{"log2n": 3, "grid": 0, "tail": 1}]}',
                 '{"entries": [{"log2n": 3, "grid": 1, "tail": -1}]}', '{"entries": [{"log2n": 3, "grid": 1',
-                '{"entries": [], "engine_grid": 0}', '{"entries": [], "engine_grid": 100000}']:
+                '{"entries": [], "engine_grid": 0}', '{"entries": [], "engine_grid": 100000}',
+                '{"entries": [{"log2n": 3, "grid": 1, "tail": 1, "stream": 2}]}',
+                '{"entries": [{"log2n": 3, "grid": 1, "tail": 1, "sgrid": 5000}]}']:
         assert sqh.sqh_set_tuning(H.ctx, bad) == sqh.SQH_EINVAL, bad
     assert H.tuning() == '{"entries": []}'
     H.set_tuning('{"entries": [], "engine_grid": 17}')
@@ -83,13 +86,26 @@ def test_tuning_text_rejected(H):
     assert H.tuning() == '{"entries": []}'
 
 
+@pytest.mark.parametrize("sgrid", [1024, 512, 256, 64])
+def test_streaming_shapes_same_hull(H, sgrid):
+    import torch
+    say(f"streaming kernels on {sgrid} workgroups")
+    H.set_tuning('{"entries": [{"log2n": 20, "grid": 1, "tail": 0, "stream": 1, "sgrid": %d}]}' % sgrid)
+    for kind, n in (("square", 1_000_003), ("disk", 300_001), ("circle", 200_000), ("grid", 300_000)):
+        xy = workloads.make(kind, n, 12)
+        got = [int(v) for v in H.hull(torch.from_numpy(xy).cuda()).cpu().numpy()]
+        assert got == expect_hull(xy), (kind, sgrid)
+        assert H.stats()["stream_path"] in (1, 2)
+    H.set_tuning('{"entries": []}')
+
+
 def test_autotune_then_same_hull(H):
     import torch
     say("autotune square 1M")
     xy = workloads.square(1_000_000, 3)
     t = torch.from_numpy(xy).cuda()
     text = H.autotune(t, reps=1)
-    assert '"log2n": 19' in text, text
+    assert '"log2n": 19' in text and '"stream": ' in text and '"sgrid": ' in text, text
     H.set_tuning(text)  # round trip
     assert H.tuning() == text
     got = [int(v) for v in H.hull(t).cpu().numpy()]

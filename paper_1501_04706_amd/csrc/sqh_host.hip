@@ -342,12 +342,20 @@ inline int call_launches(const HullArgs& a, Launch (&L)[kMaxLaunches], bool fall
     }
     return n;
 }
+// Streaming kernels: a tuned grid applies to all of them; by default the
+// first compaction runs two workgroups per co-resident one (its tiles wait
+// on a reservation round trip, which a second workgroup per compute unit
+// hides) and the others one (fewer partials for the last workgroup to
+// reduce: 35 us instead of 48 for the seed of 20M points).
 inline dim3 launch_grid(const Launch& l, int grid, int sgrid)
 {
     if (l.f == reinterpret_cast<const void*>(k_stail)) return dim3(1);
     if (l.light) return dim3(kLightGrid);
     if (l.coop) return dim3(grid);
-    return dim3(sgrid > 0 ? std::min(sgrid, kMaxSGrid) : std::min(2 * grid, kMaxSGrid));
+    if (sgrid > 0) return dim3(std::min(sgrid, kMaxSGrid));
+    const bool first = l.f == reinterpret_cast<const void*>(k_sfirst<true>) ||
+                       l.f == reinterpret_cast<const void*>(k_sfirst<false>);
+    return dim3(std::min(first ? 2 * grid : grid, kMaxSGrid));
 }
 inline dim3 launch_block(const Launch& l)
 {

@@ -1396,7 +1396,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
     if (S <= 0 || S > kSPassMaxS || V <= kSPassMinV || pass >= kMaxInfoPasses) return;  // uniform
     const SeedPart sr = uni(gld(&ws->seed_res));
     const bool sline = sr.line && !fp64;
-    const float Mx = sr.Mx, My = sr.My, ext = fmaxf(sr.mxx - sr.mnx, sr.yhi - sr.ylo);
+    const float Mx = sr.Mx, My = sr.My;
     // the segment table and each segment's first tile
     {
         SSeg g = {};
@@ -1458,10 +1458,15 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
                 x[r] = gld(Xi + p); y[r] = gld(Yi + p); id[r] = gld(Ii + p);
             }
             uint32_t pend = 0u;
-            // the line filter where the segment spans at least 1/16 of the
-            // input's extent (its bound grows with the extent; the
-            // orientation filter's with the distances inside the segment)
-            const bool line = sline && fmaxf(fabsf(g.bx - g.ax), fabsf(g.by - g.ay)) * 16.0f >= ext;
+            // the line filter where the farthest point's area is large
+            // against the line bound of A->B (the areas of the children's
+            // points are on that scale; the line bound grows with the
+            // input's extent, the orientation filter's with the distances
+            // inside the segment, which wins on short, flat segments)
+            const float dxs = g.bx - g.ax, dys = g.by - g.ay;
+            const float mab = (fabsf(dxs) * My + fabsf(dys) * Mx) * kLineRel;
+            const float acb = fabsf(dxs * (g.cy - g.ay) - dys * (g.cx - g.ax));
+            const bool line = sline && acb > 1024.0f * mab;
             if (line) {
                 const LineF L0 = make_line(g.ax, g.ay, g.cx, g.cy, Mx, My);
                 const LineF L1 = make_line(g.cx, g.cy, g.bx, g.by, Mx, My);

@@ -1385,6 +1385,10 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
     __shared__ int s_wbase[kSWaves][2];
     __shared__ int s_base[2];
     __shared__ Pair s_red[kSWaves];
+    // each thread's points of the current tile, for the scatter (read back
+    // only by the thread that wrote them)
+    __shared__ float s_px[kPRows][kSBlock], s_py[kPRows][kSBlock];
+    __shared__ int s_pi[kPRows][kSBlock];
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int fp64 = a.fp64;
@@ -1456,6 +1460,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
                 const bool m = full | (pos < g.len);
                 const int p = g.off + (m ? pos : 0);
                 x[r] = gld(Xi + p); y[r] = gld(Yi + p); id[r] = gld(Ii + p);
+                s_px[r][t] = x[r]; s_py[r][t] = y[r]; s_pi[r][t] = id[r];
             }
             uint32_t pend = 0u;
             // the line filter where the farthest point's area is large
@@ -1539,19 +1544,17 @@ __global__ __launch_bounds__(kSBlock, 4) void k_spass(HullArgs a)
         }
         __syncthreads();
         {
-            // scatter (the tile is read again, from the L2 cache)
+            // scatter (the tile from this thread's LDS copy)
             int run0 = s_base[0] + s_wbase[w][0], run1 = s_base[1] + s_wbase[w][1];
 #pragma unroll
             for (int r = 0; r < kPRows; ++r) {
-                const int pos = q0pos + 64 * r + lane;
                 const int c = (int)(code >> (4 * r)) & 15;
                 const uint64_t M0 = __ballot(c == 0), M1 = __ballot(c == 1);
                 const int dst = c == 0 ? g.off + run0 + lanes_below(M0) : g.off + g.len - 1 - (run1 + lanes_below(M1));
                 if (c < 2) {
-                    const int p = g.off + pos;
-                    gst(Xo + dst, gld(Xi + p));
-                    gst(Yo + dst, gld(Yi + p));
-                    gst(Io + dst, gld(Ii + p));
+                    gst(Xo + dst, s_px[r][t]);
+                    gst(Yo + dst, s_py[r][t]);
+                    gst(Io + dst, s_pi[r][t]);
                 }
                 run0 += __popcll(M0);
                 run1 += __popcll(M1);

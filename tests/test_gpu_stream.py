@@ -215,3 +215,19 @@ def test_soa_input_errors(H):
     rc, _ = sqh.sqh_hull_soa(H.ctx, x, x, 10, out, 10, ws, 16)
     assert rc == sqh.SQH_ENOMEM
     assert sqh.sqh_workspace_bytes_soa(-1) == 0
+
+
+@pytest.mark.parametrize("ring", [900, 3000, 6000])
+def test_stream_lds_tail_hand_over(H, ring):
+    # few hull points around many interior ones: the first compaction leaves
+    # about `ring` points, which the LDS passes take; a ring of more than
+    # 1024 points outgrows the LDS table (more than 512 segments with more
+    # than 1024 points left) and is written back for the passes kernel
+    n = THRESHOLD + 1000
+    say(f"LDS tail: ring of {ring} in {n}")
+    inner = workloads.disk(n - ring, 21) * np.float32(0.5)
+    outer = workloads.circle(ring, 22)
+    xy = np.ascontiguousarray(np.concatenate([inner, outer], 0).astype(np.float32))
+    got, st = run(H, xy)
+    assert got == [int(v) for v in oracle.c_hull(xy)]
+    assert st["stream_path"] == (1 if ring <= 1024 else 2)

@@ -1147,7 +1147,13 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int fp64 = a.fp64;
     const int n = a.N;
-    const int ntiles = (n + kSTile - 1) / kSTile;
+    // each workgroup takes one contiguous range of whole rows (the same
+    // share for all, so that none runs a tile more than the others); the
+    // last tile of a range is partial, and its waves past the end skip it
+    const int npairs = (n + 1) >> 1;
+    const int per = (((npairs + nb - 1) / nb) + 63) & ~63;
+    const int pb = min(b * per, npairs), pe = min(pb + per, npairs);
+    const int nend = min(n, 2 * pe);  // points of this range: ids below nend
     const float2* xy = a.xy;
     float* X = a.X[0];
     float* Y = a.Y[0];
@@ -1181,43 +1187,47 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     }
     s.n_orient_exact = 0u;
     s.n_cmp_exact = 0u;
-    uint32_t n_orient = 0u;
-    for (int j = b; j < ntiles; j += nb) {
-        const int p0 = tile_pair0(j, w) + lane;
-        s.code_lo = 0u;
-        s.code_hi = 0u;  // 4 bits per point i = 2 row + h: rows 0-3 / 4-7
-        {
+    uint32_t wave_pts = 0u;  // points this wave classified (the same in every lane)
+    for (int q = pb; q < pe; q += kSTilePairs) {
+        const int wp0 = q + w * (kSRows * 64);  // this wave's first pair
+        const int p0 = wp0 + lane;
+        const bool live = 2 * wp0 < nend;       // uniform: the wave has points
+        s.code_lo = 0x77777777u;
+        s.code_hi = 0x77777777u;  // 4 bits per point i = 2 row + h: rows 0-3 / 4-7 (7: none)
+        int wc[4] = {0, 0, 0, 0};
+        if (live) {
+            s.code_lo = 0u;
+            s.code_hi = 0u;
             float4 v[kSRows];
-            load_rows(xy, n, p0, tile_pair0(j, w), v);
+            load_rows(xy, nend, p0, wp0, v);
 #pragma unroll
             for (int rr = 0; rr < kSRows; ++rr) s_tile[rr][t] = v[rr];
             // filter-only pass; points needing an exact decision are settled
             // afterwards, one at a time
             if constexpr (LINE) {
-                const uint32_t pend = first_line_rows(s, v, p0, n, L);
-                n_orient += 4u * lane_points(n, p0, tile_pair0(j, w));
+                const uint32_t pend = first_line_rows(s, v, p0, nend, L);
+                wave_pts += (uint32_t)min(nend - 2 * wp0, 2 * 64 * kSRows);
                 if (__ballot(pend != 0u)) {
                     Lane tmp = s;
                     first_pending_line(&tmp, pend, p0, g, L, xy);
                     s = tmp;
                 }
             } else {
-                const uint32_t pend = first_fast_rows(s, v, p0, n, g, fp64 != 0);
-                n_orient += 3u * lane_points(n, p0, tile_pair0(j, w));
+                const uint32_t pend = first_fast_rows(s, v, p0, nend, g, fp64 != 0);
+                wave_pts += (uint32_t)min(nend - 2 * wp0, 2 * 64 * kSRows);
                 if (__ballot(pend != 0u)) {
                     Lane tmp = s;
                     first_pending(&tmp, pend, p0, g, xy, fp64);
                     s = tmp;
                 }
             }
-        }
-        int wc[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 2 * kSRows; ++i) {
-            const int sh = 4 * (i & 7);
-            const int code = (int)(((i < 8) ? s.code_lo : s.code_hi) >> sh) & 15;
+            for (int i = 0; i < 2 * kSRows; ++i) {
+                const int sh = 4 * (i & 7);
+                const int code = (int)(((i < 8) ? s.code_lo : s.code_hi) >> sh) & 15;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) wc[k] += __popcll(__ballot(code == k));
+                for (int k = 0; k < 4; ++k) wc[k] += __popcll(__ballot(code == k));
+            }
         }
         if (lane == 0) {
 #pragma unroll
@@ -1234,7 +1244,7 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
             s_base[t] = run > 0 ? (int)atomicAdd(&ws->cursor[t], (unsigned int)run) : 0;
         }
         __syncthreads();
-        {
+        if (live) {
             // scatter: ranks inside a row from ballots, so that each row
             // writes one contiguous run per child
             float4 v[kSRows];
@@ -1296,6 +1306,7 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     } else {
         first_wg_partial(&ws->first[b], s, g, xy, fp64);
     }
+    const uint32_t n_orient = lane == 0 ? (LINE ? 4u : 3u) * (uint32_t)uni((int)wave_pts) : 0u;
     Counters ctr = {n_orient, s.n_orient_exact, s.n_cmp_exact};
     flush_counters(a.stats, ctr);
     if (last_arrival(&ws->done[2], nb)) {

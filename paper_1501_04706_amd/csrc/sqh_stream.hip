@@ -310,9 +310,8 @@ struct StreamWs {
 };
 __device__ __forceinline__ PassRec* pass_recs(void* ws) { return reinterpret_cast<PassRec*>(static_cast<StreamWs*>(ws) + 1); }
 
-// the pairs of one wave's rows in tile j: pair index of row r, lane l is
-// p0 + 64 r + l
-__device__ __forceinline__ int tile_pair0(int j, int w) { return j * kSTilePairs + w * (kSRows * 64); }
+// A wave holds kSRows rows of a tile: with wp0 its first pair, row r of
+// lane l is pair wp0 + 64 r + l.
 
 // Loads pair p (points 2p and 2p + 1; npf full pairs, plus one point if
 // odd). Point 2p + h exists iff 2p + h < n.
@@ -326,6 +325,17 @@ __device__ __forceinline__ float4 load_pair(const float2* xy, int npf, int odd, 
         v.x = t.x; v.y = t.y;
     }
     return v;
+}
+
+// The contiguous range of pairs [pb, pe) that workgroup b of nb takes: an
+// equal share of whole rows for every workgroup, so that none runs a tile
+// more than the others.
+__device__ __forceinline__ void wg_range(int n, int b, int nb, int& pb, int& pe)
+{
+    const int npairs = (n + 1) >> 1;
+    const int per = (((npairs + nb - 1) / nb) + 63) & ~63;
+    pb = min(b * per, npairs);
+    pe = min(pb + per, npairs);
 }
 
 // Points this lane holds in its wave's rows of a tile (pairs p0 + 64 r).
@@ -969,24 +979,28 @@ __global__ __launch_bounds__(kSBlock) void k_sseed(HullArgs a)
     const int b = (int)blockIdx.x, nb = (int)gridDim.x;
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int n = a.N;
-    const int ntiles = (n + kSTile - 1) / kSTile;
+    int pb, pe;
+    wg_range(n, b, nb, pb, pe);
+    const int nend = min(n, 2 * pe);  // points of this workgroup's range: ids below nend
     const float2* xy = a.xy;
     auto* ws = static_cast<StreamWs*>(a.sws);
     if (b == 0 && t == 0) stamp_here(a, 0);
     Lex mn = {INFINITY, INFINITY, 0x7fffffff}, mx = {-INFINITY, -INFINITY, 0x7fffffff};
     float ylo = INFINITY, yhi = -INFINITY;
     bool bad = false;
-    for (int j = b; j < ntiles; j += nb) {
-        const int p0 = tile_pair0(j, w) + lane;
+    // each wave takes every kSWaves-th block of rows of the range (waves
+    // do not wait for each other here)
+    for (int wp0 = pb + w * (kSRows * 64); wp0 < pe; wp0 += kSTilePairs) {
+        const int p0 = wp0 + lane;
         float4 v[kSRows];
-        load_rows(xy, n, p0, tile_pair0(j, w), v);
+        load_rows(xy, nend, p0, wp0, v);
 #pragma unroll
         for (int r = 0; r < kSRows; ++r) {
             const int id0 = 2 * (p0 + 64 * r);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
-                const bool m = id0 + h < n;
+                const bool m = id0 + h < nend;
                 bad |= m & !((int)isfinite(x) & (int)isfinite(y));
                 ylo = m ? fminf(ylo, y) : ylo;
                 yhi = m ? fmaxf(yhi, y) : yhi;
@@ -1044,7 +1058,9 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
     const int lane = lane_id(), w = wave_index();
     const int fp64 = a.fp64;
     const int n = a.N;
-    const int ntiles = (n + kSTile - 1) / kSTile;
+    int pb, pe;
+    wg_range(n, b, nb, pb, pe);
+    const int nend = min(n, 2 * pe);  // points of this workgroup's range: ids below nend
     const float2* xy = a.xy;
     auto* ws = static_cast<StreamWs*>(a.sws);
     const SeedPart sr = uni(gld(&ws->seed_res));
@@ -1057,10 +1073,10 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
     s.c0 = 0; s.c1 = 0;
     s.n_orient_exact = 0u; s.n_cmp_exact = 0u;
     uint32_t n_orient = 0u;
-    for (int j = b; j < ntiles; j += nb) {
-        const int p0 = tile_pair0(j, w) + lane;
+    for (int wp0 = pb + w * (kSRows * 64); wp0 < pe; wp0 += kSTilePairs) {  // as in the seed
+        const int p0 = wp0 + lane;
         float4 v[kSRows];
-        load_rows(xy, n, p0, tile_pair0(j, w), v);
+        load_rows(xy, nend, p0, wp0, v);
         // filter-only pass; points needing an exact decision are settled
         // afterwards, out of line (the pass neither counts nor offers them)
         uint32_t pend = 0u;
@@ -1071,7 +1087,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
-                    const bool m = id0 + h < n;
+                    const bool m = id0 + h < nend;
                     const float tt = line_eval(L, x, y);
                     const bool neg = tt < -L.m, pos = tt > L.m;
                     // lower side: the area for A->B is -orient; upper: for B->A it is orient
@@ -1093,7 +1109,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const float x = h ? v[r].z : v[r].x, y = h ? v[r].w : v[r].y;
-                    const bool m = id0 + h < n;
+                    const bool m = id0 + h < nend;
                     const Orient32 o = orient32p(ax, ay, bx, by, x, y);
                     const int sg = fsign(o, fp64 != 0);
                     const float ar = sg < 0 ? -o.d : o.d, wr = 2.0f * o.es;
@@ -1108,7 +1124,7 @@ __global__ __launch_bounds__(kSBlock, 4) void k_ssplit(HullArgs a)
                 }
             }
         }
-        n_orient += lane_points(n, p0, tile_pair0(j, w));
+        n_orient += lane_points(nend, p0, wp0);
         if (__ballot(pend != 0u)) {
             SplitLane tmp = s;
             split_pending(&tmp, pend, p0, ax, ay, bx, by, xy, fp64);
@@ -1147,12 +1163,10 @@ __device__ __forceinline__ void sfirst_body(const HullArgs& a)
     const int t = (int)threadIdx.x, lane = lane_id(), w = wave_index();
     const int fp64 = a.fp64;
     const int n = a.N;
-    // each workgroup takes one contiguous range of whole rows (the same
-    // share for all, so that none runs a tile more than the others); the
-    // last tile of a range is partial, and its waves past the end skip it
-    const int npairs = (n + 1) >> 1;
-    const int per = (((npairs + nb - 1) / nb) + 63) & ~63;
-    const int pb = min(b * per, npairs), pe = min(pb + per, npairs);
+    // one contiguous range of rows per workgroup; the last tile of a range
+    // is partial, and its waves past the end skip it
+    int pb, pe;
+    wg_range(n, b, nb, pb, pe);
     const int nend = min(n, 2 * pe);  // points of this range: ids below nend
     const float2* xy = a.xy;
     float* X = a.X[0];

@@ -47,6 +47,22 @@ struct Layout {
     size_t bytes;
 };
 
+// The status block read back after every call: the error word, the
+// counters, the set and vertex counts and the info block are consecutive
+// takes of every layout below; offsets from the error word.
+struct StatusOffsets {
+    size_t stats, info, bytes;
+};
+StatusOffsets status_offsets()
+{
+    StatusOffsets so;
+    so.stats = align_up(sizeof(int));
+    const size_t sv = so.stats + align_up(sizeof(uint32_t) * 4 * kStatSlots);
+    so.info = sv + align_up(sizeof(int) * 4);
+    so.bytes = so.info + sizeof(HullInfo);
+    return so;
+}
+
 bool make_layout(int64_t N, int64_t nsets, Layout& L)
 {
     if (N < 0 || nsets < 1 || N > (int64_t)INT32_MAX - 2 || nsets > (int64_t)INT32_MAX / 8) return false;
@@ -152,9 +168,10 @@ struct sqh_ctx {
     int max_grid = 0;  // co-resident workgroups of k_hull
     int trace = 0;     // SQH_TRACE=1: per-workgroup timestamps in the info block
     hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
-    HullInfo* hinfo = nullptr;   // pinned host copy of the info block
-    uint32_t* hstats = nullptr;  // pinned host copy of the counters
-    int* herr = nullptr;
+    unsigned char* hstatus = nullptr;  // pinned host copy of the status block (status_offsets)
+    HullInfo* hinfo = nullptr;   // ... its info block
+    uint32_t* hstats = nullptr;  // ... its counters
+    int* herr = nullptr;         // ... its error word
     sqh_stats stats{};
     static constexpr int kMaxTune = 40;
     TuneEntry tune[kMaxTune];
@@ -433,10 +450,17 @@ void phase_times(const HullInfo& hi, sqh_stats& S);
 int collect(sqh_ctx* ctx, const HullArgs& a, int64_t N, int64_t out_cap, int64_t* h_total, hipStream_t st,
             bool timed)
 {
-    HIP_OK(hipMemcpyAsync(ctx->hinfo, a.info, ctx->trace ? sizeof(HullInfo) : offsetof(HullInfo, trace),
-                          hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(ctx->hstats, a.stats, sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(ctx->herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    const size_t info_bytes = ctx->trace ? sizeof(HullInfo) : offsetof(HullInfo, trace);
+    const StatusOffsets so = status_offsets();
+    const char* d0 = reinterpret_cast<const char*>(a.err);
+    if (reinterpret_cast<const char*>(a.stats) == d0 + so.stats && reinterpret_cast<const char*>(a.info) == d0 + so.info) {
+        // one copy of the whole block (each copy is a launch on the stream)
+        HIP_OK(hipMemcpyAsync(ctx->hstatus, a.err, so.info + info_bytes, hipMemcpyDeviceToHost, st));
+    } else {
+        HIP_OK(hipMemcpyAsync(ctx->hinfo, a.info, info_bytes, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(ctx->hstats, a.stats, sizeof(uint32_t) * 4 * kStatSlots, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(ctx->herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
     HIP_OK(hipStreamSynchronize(st));
 
     const HullInfo& hi = *ctx->hinfo;
@@ -759,12 +783,16 @@ int sqh_create(sqh_ctx** out, int device)
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->evk) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), sizeof(HullInfo), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->hstats), sizeof(uint32_t) * 4 * kStatSlots,
-                      hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->herr), sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&c->hstatus), status_offsets().bytes, hipHostMallocDefault) !=
+            hipSuccess) {
         sqh_destroy(c);
         return SQH_EDEVICE;
+    }
+    {
+        const StatusOffsets so = status_offsets();
+        c->herr = reinterpret_cast<int*>(c->hstatus);
+        c->hstats = reinterpret_cast<uint32_t*>(c->hstatus + so.stats);
+        c->hinfo = reinterpret_cast<HullInfo*>(c->hstatus + so.info);
     }
     *out = c;
     return SQH_OK;
@@ -778,9 +806,7 @@ void sqh_destroy(sqh_ctx* c)
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->evk) (void)hipEventDestroy(c->evk);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->hinfo) (void)hipHostFree(c->hinfo);
-    if (c->hstats) (void)hipHostFree(c->hstats);
-    if (c->herr) (void)hipHostFree(c->herr);
+    if (c->hstatus) (void)hipHostFree(c->hstatus);
     delete c;
 }
 

@@ -39,7 +39,7 @@ constexpr int kSBlock = kSWaves * 64;
 constexpr int kMaxSGrid = 1024;               // workgroups of a streaming launch (upper bound)
 constexpr int kSRows = 8;                     // rows of point pairs per wave and tile
 constexpr int kSTilePairs = kSBlock * kSRows;  // pairs per workgroup tile
-constexpr int kSTile = 2 * kSTilePairs;       // points per workgroup tile (16384)
+constexpr int kSTile = 2 * kSTilePairs;       // points per workgroup tile (8192)
 constexpr int kStreamMin = 1 << 16;           // single hulls of at least this many points take this path
 
 // Farthest-point candidate of one lane: the area interval [lo, hi] =

@@ -1744,6 +1744,25 @@ __device__ __forceinline__ void lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// block_excl_scan with barriers that order LDS only: a pass of the LDS tail
+// does not wait here for its vertex records and counters to reach memory.
+__device__ __forceinline__ Pair lds_excl_scan(Pair v, Pair* red, Pair* tot)
+{
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const Pair inc = {wave_incl_sum(v.a), wave_incl_sum(v.b)};
+    lds_sync();
+    if (lane == 63) red[w] = inc;
+    lds_sync();
+    Pair off = {0, 0}, all = {0, 0};
+#pragma unroll
+    for (int u = 0; u < kWaves; ++u) {
+        if (u < w) { off.a += red[u].a; off.b += red[u].b; }
+        all.a += red[u].a; all.b += red[u].b;
+    }
+    *tot = all;
+    return Pair{off.a + inc.a - v.a, off.b + inc.b - v.b};
+}
+
 // float -> unsigned with the same order
 __device__ __forceinline__ unsigned okey(float f)
 {
@@ -1944,7 +1963,7 @@ __device__ __forceinline__ bool lds_passes(const HullArgs& a, int cur, int pass,
             n1 = L.cnt[2 * t + 1];
         }
         Pair tot;
-        const Pair ex = block_excl_scan(Pair{n0 + n1, (n0 > 0) + (n1 > 0)}, red, &tot);
+        const Pair ex = lds_excl_scan(Pair{n0 + n1, (n0 > 0) + (n1 > 0)}, red, &tot);
         if (t < S) {
             // C is a vertex: its key is the first slot after the (A, C) points
             const int key = mine.off + n0;

@@ -72,10 +72,14 @@ def test_below_threshold_takes_general_path(H):
 @pytest.mark.parametrize("mode", [sqh.SQH_FP32_FILTER, sqh.SQH_FP32_SEMISTATIC, sqh.SQH_FP64_ONLY])
 def test_stream_precision_modes(H, mode):
     say(f"precision mode {mode}: square n=2000003")
-    xy = workloads.square(2_000_003, 13)
+    n = 2_000_003
+    xy = workloads.square(n, 13)
     got, st = run(H, xy, precision=mode)
     assert st["stream_path"] in (1, 2)
     assert st["line_filter"] == (1 if mode == sqh.SQH_FP32_FILTER else 0)
+    # one test per point in the split, three or four in the first
+    # compaction, two per point of each later pass (with room to spare)
+    assert 0 < st["orient_evals"] <= 6 * n + 4 * sum(st["pass_points"])
     if mode == sqh.SQH_FP64_ONLY:
         # the first compaction charges three tests per point; a point
         # settled by its first exact test takes fewer
